@@ -1,0 +1,203 @@
+"""Seeded synthetic inputs for the HMCSC workloads.
+
+Each generator returns host arrays only: the bounce-back-fraction field(s)
+``ns[k, z, y, x]`` (float32) and initial component densities ``rho[s, z, y, x]``
+(float64).  Nothing here computes any part of the lattice Boltzmann method; both
+the GPU library and the CPU checker consume these arrays unchanged.
+
+Random numbers come from ``numpy.random.Generator(PCG64(seed))``.
+
+Workloads (the paper's own 3-D microstructure and separator images are not
+available, these synthetic stand-ins have the same structure):
+
+* ``droplet``        static droplet in a uniform gray medium (bubble test, Sec. 3.3)
+* ``gray_channel``   walls plus a gray slab between free fluid (Sec. 3.2, Brinkman flow)
+* ``electrode``      random overlapping spheres + smoothed gray binder + reservoirs
+                     (electrolyte filling, Sec. 4)
+* ``porous_domain``  random-sphere packing with a smoothed gray field (ensembles)
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@dataclass
+class Workload:
+    """Arrays and parameters of one problem (x fastest in every array)."""
+    shape: tuple                      # (nx, ny, nz)
+    ns: np.ndarray                    # float32 [c_ns, nz, ny, nx]
+    rho: np.ndarray                   # float64 [ncomp, nz, ny, nx]
+    ncomp: int = 2
+    tau: tuple = (1.0, 1.0)
+    G: float = 0.0
+    G_ads: tuple = (0.0, 0.0)
+    F_ext: tuple = (0.0, 0.0, 0.0)
+    g_scale: float = 3.0
+    reservoirs: list = field(default_factory=list)  # [(axis, lo, hi, (rho_1, rho_2))]
+    name: str = ""
+
+    @property
+    def c_ns(self) -> int:
+        return int(self.ns.shape[0])
+
+    @property
+    def ncells(self) -> int:
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+
+def uniform(shape, ns_value=0.0, rho=(1.0, 0.0), ncomp=2) -> Workload:
+    nx, ny, nz = shape
+    ns = np.full((1, nz, ny, nx), ns_value, np.float32)
+    r = np.empty((ncomp, nz, ny, nx))
+    for s in range(ncomp):
+        r[s] = rho[s]
+    return Workload(shape, ns, r, ncomp=ncomp, name="uniform")
+
+
+def random_state(shape, seed, ncomp=2, c_ns=1, ns_choices=None, rho_range=(0.05, 1.0)) -> Workload:
+    """Random densities and a random bounce-back field (values drawn from
+    ``ns_choices`` when given, e.g. to include exact 0 and 1, else U[0,1))."""
+    nx, ny, nz = shape
+    g = rng(seed)
+    if ns_choices is None:
+        ns = g.uniform(0.0, 1.0, size=(c_ns, nz, ny, nx)).astype(np.float32)
+    else:
+        ns = g.choice(np.asarray(ns_choices, np.float32), size=(c_ns, nz, ny, nx))
+    r = g.uniform(rho_range[0], rho_range[1], size=(ncomp, nz, ny, nx))
+    return Workload(shape, ns.astype(np.float32), r, ncomp=ncomp, name=f"random{seed}")
+
+
+def droplet(n=32, radius=8.0, ns_value=0.1, rho_in=1.0, rho_out=0.03, noise=1e-3, seed=0,
+            G=0.9, tau=1.0) -> Workload:
+    """Sphere of component A (densities rho_in / rho_out inside, swapped outside),
+    centred at ((n-1)/2)^3, inside when |x - c|^2 <= R^2, plus U(-noise, noise) per
+    component and cell drawn component-major then z, y, x."""
+    c = (n - 1) / 2.0
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    inside = (x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2 <= radius * radius
+    r = np.empty((2, n, n, n))
+    r[0] = np.where(inside, rho_in, rho_out)
+    r[1] = np.where(inside, rho_out, rho_in)
+    if noise:
+        r += rng(seed).uniform(-noise, noise, size=r.shape)
+    ns = np.full((1, n, n, n), ns_value, np.float32)
+    return Workload((n, n, n), ns, r, ncomp=2, tau=(tau, tau), G=G, name=f"droplet{n}")
+
+
+def gray_channel(nx=64, ny=64, nz=128, slab=(24, 40), ns_slab=0.1, force=1e-6, tau=0.8) -> Workload:
+    """Single component between walls (n_s = 1 at y = 0 and y = ny-1) with a gray
+    slab ``slab[0] <= y < slab[1]`` of bounce-back fraction ``ns_slab``, free fluid
+    elsewhere, body force along z."""
+    ns = np.zeros((1, nz, ny, nx), np.float32)
+    ns[0, :, slab[0]:slab[1], :] = ns_slab
+    ns[0, :, 0, :] = 1.0
+    ns[0, :, ny - 1, :] = 1.0
+    r = np.ones((1, nz, ny, nx))
+    return Workload((nx, ny, nz), ns, r, ncomp=1, tau=(tau, tau), F_ext=(0.0, 0.0, force),
+                    name=f"channel_ns{ns_slab}")
+
+
+def _gaussian_smooth(a: np.ndarray, sigma: float) -> np.ndarray:
+    from scipy.ndimage import gaussian_filter
+    return gaussian_filter(a, sigma=sigma, mode="wrap")
+
+
+def _sphere_pack(shape, g, target_solid, rmin, rmax, zlo=0, zhi=None, batch=64):
+    """Overlapping spheres (centres U[0,n)^3, radius U[rmin,rmax]) painted with
+    periodic minimum image in x and y until the solid fraction inside
+    ``zlo <= z < zhi`` reaches ``target_solid``.  Returns a bool [nz, ny, nx]."""
+    nx, ny, nz = shape
+    zhi = nz if zhi is None else zhi
+    solid = np.zeros((nz, ny, nx), bool)
+    vol = (zhi - zlo) * ny * nx
+    count = 0
+    while solid[zlo:zhi].sum() < target_solid * vol:
+        for _ in range(batch):
+            cx, cy, cz = g.uniform(0, nx), g.uniform(0, ny), g.uniform(0, nz)
+            R = g.uniform(rmin, rmax)
+            r0 = int(np.ceil(R))
+            xs = np.arange(int(np.floor(cx)) - r0, int(np.floor(cx)) + r0 + 2)
+            ys = np.arange(int(np.floor(cy)) - r0, int(np.floor(cy)) + r0 + 2)
+            zs = np.arange(max(int(np.floor(cz)) - r0, zlo), min(int(np.floor(cz)) + r0 + 2, zhi))
+            if len(zs) == 0:
+                continue
+            dz = (zs - cz)[:, None, None]
+            dy = (ys - cy)[None, :, None]
+            dx = (xs - cx)[None, None, :]
+            m = dx * dx + dy * dy + dz * dz <= R * R
+            zi, yi, xi = np.nonzero(m)
+            solid[zs[zi], ys[yi] % ny, xs[xi] % nx] = True
+            count += 1
+        if count > 10_000_000:
+            raise RuntimeError("sphere packing did not reach the target")
+    return solid
+
+
+def electrode(n=256, seed=2000, res_layers=16, solid_fraction=0.5, rmin=6.0, rmax=12.0,
+              binder_frac=0.2, G=0.9, G_ads=(-0.3, 0.3), rho_main=1.0, rho_dis=0.03,
+              tau=1.0) -> Workload:
+    """Synthetic electrode for the electrolyte-filling workload.
+
+    * spheres (n_s = 1) of radius U[rmin, rmax] fill ``res_layers <= z < n-res_layers``
+      to the solid fraction ``solid_fraction`` (periodic in x, y; none in the reservoirs)
+    * binder: white noise, Gaussian-smoothed (sigma 3), thresholded at its
+      (1-binder_frac) quantile over the pore cells; binder n_s =
+      clip(0.5 + 0.15 * zscore, 0.2, 0.8)
+    * component A (wetting, index 0) fills the inlet reservoir z < res_layers,
+      component B fills everything else; reservoirs hold (rho_main, rho_dis) at the
+      inlet and (rho_dis, rho_main) at the outlet.
+    """
+    g = rng(seed)
+    shape = (n, n, n)
+    zlo, zhi = res_layers, n - res_layers
+    solid = _sphere_pack(shape, g, solid_fraction, rmin, rmax, zlo, zhi)
+    noise = _gaussian_smooth(g.standard_normal((n, n, n)), 3.0)
+    pore = ~solid
+    pore[:zlo] = False
+    pore[zhi:] = False
+    vals = noise[pore]
+    thr = np.quantile(vals, 1.0 - binder_frac)
+    binder = pore & (noise >= thr)
+    zscore = (noise - vals.mean()) / vals.std()
+    ns = np.zeros((1, n, n, n), np.float32)
+    ns[0][binder] = np.clip(0.5 + 0.15 * zscore[binder], 0.2, 0.8)
+    ns[0][solid] = 1.0
+    r = np.empty((2, n, n, n))
+    r[0] = rho_dis
+    r[1] = rho_main
+    r[0, :zlo] = rho_main
+    r[1, :zlo] = rho_dis
+    res = [(2, 0, zlo, (rho_main, rho_dis)), (2, zhi, n, (rho_dis, rho_main))]
+    return Workload(shape, ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads),
+                    reservoirs=res, name=f"electrode{n}")
+
+
+def porous_domain(edge, seed, porosity=None, ns_max=0.9, G=0.9, G_ads=(0.1, -0.1),
+                  force=1e-5, rho_main=1.0, rho_dis=0.03, tau=1.0) -> Workload:
+    """Cubic random-sphere packing (porosity U[0.35, 0.65] unless given) with a
+    gray field n_s = ns_max * minmax(smoothed noise) in the pores; component A in
+    the pore space of z < edge/4, B elsewhere; body force along z."""
+    g = rng(seed)
+    if porosity is None:
+        porosity = g.uniform(0.35, 0.65)
+    n = int(edge)
+    solid = _sphere_pack((n, n, n), g, 1.0 - porosity, max(2.0, n / 24), max(3.0, n / 12), batch=16)
+    noise = _gaussian_smooth(g.standard_normal((n, n, n)), 3.0)
+    lo, hi = noise.min(), noise.max()
+    gray = ns_max * (noise - lo) / (hi - lo if hi > lo else 1.0)
+    ns = np.where(solid, 1.0, gray).astype(np.float32)[None]
+    r = np.empty((2, n, n, n))
+    r[0] = rho_dis
+    r[1] = rho_main
+    quarter = max(1, n // 4)
+    r[0, :quarter][~solid[:quarter]] = rho_main
+    r[1, :quarter][~solid[:quarter]] = rho_dis
+    return Workload((n, n, n), ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads),
+                    F_ext=(0.0, 0.0, force), name=f"porous{n}_{seed}")

@@ -1,0 +1,104 @@
+"""Closed-form pins of the oracle's collision (Eqs. LGS, Maxwell, SC_u_eq,
+SC_F_ext, HMCSC_u_macro, GS_perm, Permeability).
+
+Derivations used (written out so the pins can be checked by hand):
+
+* One cell, periodic (every neighbour is the cell itself), n_s = 0, tau = 1:
+  Eq. (LGS) leaves exactly f^eq(rho_s, u^eq_s).  The second-order equilibrium
+  Eq. (Maxwell) has moments  sum f^eq = rho,  sum f^eq c = rho u,
+  sum f^eq c c = rho c_s^2 I + rho u u  (exact by the isotropy of the set).
+  The cohesion and adhesion stencils vanish on a uniform field
+  (sum_i w_i c_i = 0), so u^eq_s = u' + tau_s F_ext,s / rho_s with
+  F_ext,s = rho_s/rho F_ext (Eq. SC_F_ext).
+
+* Uniform periodic medium, uniform n_s = n, any tau_s: by the definition of u'
+  (first term of Eq. SC_u_eq) sum_s (j_s - rho_s u')/tau_s = 0, so the total
+  momentum after Eq. (LGS) is (1-n)(J + F) - n J.  Streaming a uniform field
+  changes nothing, hence the exact recurrence
+      J(t+1) = (1 - 2n) J(t) + (1 - n) F,
+      J(t)   = J_inf [1 - (1 - 2n)^t]   from J(0) = 0,   J_inf = (1-n) F / (2n),
+  and at steady state rho u_macro = (1-n)(J_inf + F/2) = (1-n)F/(2n), so the
+  Darcy permeability of Eq. (Permeability) is exactly Eq. (GS_perm):
+      k = nu <rho u> / F = (1 - n) nu / (2 n),   nu = c_s^2 (tau - 1/2).
+"""
+import numpy as np
+import pytest
+
+from oracle.ref import Setup, Oracle
+from paper_2206_11524_amd import inputs
+
+CS2 = 1.0 / 3.0
+
+
+def _moments_of_pops(f_s, c):
+    rho = f_s.sum(axis=0)
+    j = np.einsum("i...,ia->a...", f_s, c)
+    pi = np.einsum("i...,ia,ib->ab...", f_s, c, c)
+    return rho, j, pi
+
+
+@pytest.mark.parametrize("lattice", [19, 9])
+def test_single_cell_relaxes_to_second_order_equilibrium(oracle_mod, lattice):
+    c, w, _ = oracle_mod.lattice(lattice)
+    q = len(w)
+    g = np.random.Generator(np.random.PCG64(11))
+    F = np.array([1.3e-3, -0.7e-3, 0.4e-3 if lattice == 19 else 0.0])
+    tau = (1.0, 1.0)
+    st = Setup((1, 1, 1), ncomp=2, tau=tau, G=1.3, G_ads=(0.2, -0.4), F_ext=F, lattice=lattice)
+    o = Oracle(st, np.array([0.0]))
+    f = g.uniform(0.01, 0.2, size=(2, q, 1, 1, 1))
+    out = o.step(f)
+    rho_s = f.sum(axis=1)[:, 0, 0, 0]
+    j_s = np.einsum("si,ia->sa", f[:, :, 0, 0, 0], c)
+    rho = rho_s.sum()
+    up = (j_s / np.array(tau)[:, None]).sum(0) / (rho_s / np.array(tau)).sum()
+    for s in range(2):
+        ueq = up + tau[s] * (rho_s[s] / rho * F) / rho_s[s]
+        r, j, pi = _moments_of_pops(out[s, :, 0, 0, 0], c)
+        assert abs(r - rho_s[s]) < 1e-15
+        assert np.allclose(j, rho_s[s] * ueq, rtol=0, atol=1e-15)
+        d = 3 if lattice == 19 else 2
+        expect = rho_s[s] * CS2 * np.eye(3) + rho_s[s] * np.outer(ueq, ueq)
+        assert np.allclose(pi[:d, :d], expect[:d, :d], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [0.001, 0.1, 0.5, 0.9])
+def test_uniform_medium_momentum_recurrence(n):
+    """Exact transient J(t) = J_inf [1 - (1-2n)^t], two components, unequal tau."""
+    F = np.array([2e-5, -1e-5, 3e-5])
+    tau = (0.8, 1.7)
+    st = Setup((3, 4, 5), ncomp=2, tau=tau, G=0.9, G_ads=(0.3, -0.2), F_ext=F)
+    w = inputs.uniform((3, 4, 5), ns_value=n, rho=(0.7, 0.4))
+    o = Oracle(st, w.ns)
+    f = o.init(w.rho)
+    c, _, _ = __import__("oracle").lattice(19)
+    Jinf = (1 - np.float64(np.float32(n))) * F / (2 * np.float64(np.float32(n)))
+    nn = np.float64(np.float32(n))
+    for t in range(1, 41):
+        f = o.step(f)
+        J = np.einsum("si...,ia->a...", f, c)  # per cell total momentum
+        expect = Jinf * (1 - (1 - 2 * nn) ** t)
+        for a in range(3):
+            assert np.allclose(J[a], expect[a], rtol=1e-11, atol=1e-15), (t, a)
+
+
+@pytest.mark.parametrize("n", [1e-3, 0.01, 0.1, 0.5, 0.9, 0.999])
+def test_permeability_law_exact(n):
+    """Steady uniform single-component flow reproduces Eq. (GS_perm) through
+    Eq. (Permeability) with u_macro of Eq. (HMCSC_u_macro)."""
+    tau = 0.8
+    nu = CS2 * (tau - 0.5)
+    F = 1e-5
+    st = Setup((2, 2, 2), ncomp=1, tau=(tau,), F_ext=(F, 0, 0))
+    w = inputs.uniform((2, 2, 2), ns_value=n, rho=(1.0,), ncomp=1)
+    o = Oracle(st, w.ns)
+    nn = np.float64(np.float32(n))
+    # (1-2n)^t below 1e-13 of the steady value
+    steps = int(np.ceil(np.log(1e-14) / np.log(abs(1 - 2 * nn)))) + 2 if nn != 0.5 else 2
+    f = o.run(o.init(w.rho), steps)
+    m = o.moments(f)
+    rho_u = (m["rho"].sum(0) * m["u"][0]).mean()
+    k = nu * rho_u / F
+    assert abs(k / ((1 - nn) * nu / (2 * nn)) - 1) < 1e-10
+    # mass is untouched
+    assert np.allclose(m["rho"], 1.0, rtol=0, atol=1e-11)
