@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the HMCSC step on one MI355X.
+
+Workload: electrolyte filling of a synthetic electrode, 256^3 voxels, two
+components (D3Q19), random overlapping spheres (solid fraction 0.5, n_s = 1),
+gray binder (n_s in [0.2, 0.8]) in 20 % of the pore space, 16-layer density
+reservoirs at both ends of z, G_inter = 0.9, G_ads = -+0.3 (stencil weights
+sum_i W_i c_i c_i = I).  A step is one full time step of the method over the
+whole domain (forces, collision, partial bounce-back, streaming, reservoirs).
+
+Headline value: MLUPS of the plain FP32 path.  The same workload is also timed
+with shifted FP16 and BF16 storage (FP32 arithmetic).  Each variant reports
+its step kernel against the HBM roofline, with the algorithmic bytes per cell
+update B = 2*19*2*s + 4 (read and write every population once, read n_s once).
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+Q = 19
+STORE_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+
+
+def alg_bytes(storage: str, ncomp: int = 2, c_ns: int = 1) -> int:
+    return 2 * Q * ncomp * STORE_BYTES[storage] + 4 * c_ns
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lbm_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2206_11524_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(storage: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_step_electrode256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = d.get("variants", {}).get(storage)
+    return None if v is None else v.get("bytes_per_launch")
+
+
+def run_variant(w, storage, steps, warmup):
+    import torch
+    from paper_2206_11524_amd import lbm
+
+    sim = lbm.from_workload(w, storage=storage)
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kernel_ms = sim.last_step_ms()
+    tot = sim.totals()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    N = w.ncells
+    mlups = N * steps / dt / 1e6
+    B = alg_bytes(storage, w.ncomp, w.c_ns)
+    achieved = B * N / (kernel_ms * 1e-3) / 1e9
+    traffic = traffic_for(storage)
+    return {
+        "storage": storage,
+        "mlups": mlups,
+        "ms_per_step": dt / steps * 1e3,
+        "kernel_ms": kernel_ms,
+        "finite": tot["finite"],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_cell": B, "cells_per_launch": N},
+    }
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The FP64 CPU oracle on the same workload, timed on the host cores for a
+    bounded number of whole-domain steps."""
+    from oracle.ref import Oracle, Reservoir, Setup
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    res = [Reservoir(a, lo, hi, tuple(r)) for (a, lo, hi, r) in w.reservoirs]
+    st = Setup(w.shape, ncomp=w.ncomp, c_ns=w.c_ns, tau=w.tau, G=w.G, G_ads=w.G_ads, F_ext=w.F_ext,
+               g_scale=w.g_scale, reservoirs=res, nthreads=threads)
+    o = Oracle(st, w.ns.astype(np.float64))
+    f = o.init(w.rho)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f = o.step(f)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(w.ncells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full time steps of the {w.shape[0]}x{w.shape[1]}x{w.shape[2]} workload, "
+                      f"FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--edge", type=int, default=256)
+    ap.add_argument("--variants", default="f32,f16s,bf16s")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2206_11524_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    w = inputs.electrode(n=args.edge)
+    variants = [v for v in args.variants.split(",") if v]
+    results = {}
+    for v in variants:
+        results[v] = run_variant(w, v, args.steps, args.warmup)
+        print(f"# {v}: {results[v]['mlups']:.0f} MLUPS, kernel {results[v]['kernel_ms']:.3f} ms, "
+              f"{results[v]['roofline']['achieved']:.0f} GB/s", file=sys.stderr, flush=True)
+
+    head = results.get("f32") or results[variants[0]]
+    line = {
+        "metric": "MLUPS (2-comp D3Q19) + % HBM roofline; FP16-store vs FP32; p50/p99 batch latency",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"electrolyte filling, synthetic electrode {args.edge}^3, 2 components, "
+                               "D3Q19, sphere packing 0.5 solid + gray binder, z reservoirs",
+                   "cells": w.ncells, "storage": head["storage"], "parallelism": "single GPU"},
+        "roofline": head["roofline"],
+        "variants": {k: {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                         "roofline_frac": r["roofline"]["frac"], "achieved_GBs": r["roofline"]["achieved"],
+                         "traffic": r["roofline"]["traffic"], "finite": r["finite"]}
+                     for k, r in results.items()},
+    }
+    if "f32" in results and "f16s" in results:
+        line["fp16_gain_over_fp32"] = round(results["f16s"]["mlups"] / results["f32"]["mlups"], 3)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) implementation of the homogenized
+ * multi-component Shan-Chen lattice Boltzmann method (HMCSC): D3Q19, one or two
+ * fluid components, grayscale partial bounce-back weighted by a per-voxel
+ * bounce-back fraction n_s.
+ *
+ * One time step is Eq. (LGS) of Sec. 2 for every component sigma:
+ *   f_i(x + c_i, t + 1) = (1 - n_s)(f_i - (f_i - f_i^eq)/tau_sigma) + n_s f_ibar(x, t)
+ * with f^eq of Eq. (Maxwell) at the force-shifted velocity of Eq. (SC_u_eq), the
+ * forces of Eqs. (SC_F_inter), (SC_F_ads), (SC_F_ext), the D3Q19 velocity set of
+ * Appendix A, periodic streaming in x, y and z.  The bounce-back term uses the
+ * pre-collision populations of the same cell (Appendix A, Eq. LBGKWBS).
+ *
+ * Conventions shared by every call:
+ *   - Cells are indexed n = (z*ny + y)*nx + x (x fastest), N = nx*ny*nz.
+ *   - Host arrays are caller-owned; the library copies what it needs and never
+ *     keeps a host pointer after a call returns.
+ *   - "Canonical populations" are FP64 host arrays f[(s*19 + i)*N + n] holding
+ *     the pre-collision state f_i(x, t) of Eq. (LGS) at the current time t.
+ *   - Every function returns LBM_OK (0) or a negative LBM_E* code; on error
+ *     nothing is modified unless stated.
+ *   - Calls on one context are not thread-safe; distinct contexts are
+ *     independent.  Work is queued on the context's HIP stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* invalid argument or parameter               */
+#define LBM_ENOMEM (-2)    /* allocation failed / does not fit the budget */
+#define LBM_EDEVICE (-3)   /* HIP runtime error or no usable device       */
+#define LBM_EUNSTABLE (-4) /* non-finite state found by the health check  */
+#define LBM_ENOTFOUND (-5) /* unknown ticket                              */
+#define LBM_EAGAIN (-6)    /* result not ready yet                        */
+
+#define LBM_MAX_RES 4
+
+/* Storage format of the populations.  Arithmetic is FP64 for LBM_F64 and FP32
+ * otherwise.  Stored value h = (f_i - w_i*rho_shift[s]) * 2^store_scale_log2,
+ * rounded to nearest even for the 16-bit formats. */
+typedef enum {
+    LBM_F64 = 0,
+    LBM_F32 = 1,
+    LBM_F16S = 2,  /* IEEE binary16, shifted   */
+    LBM_BF16S = 3  /* bfloat16, shifted        */
+} lbm_storage;
+
+typedef struct {
+    int32_t nx, ny, nz;
+} lbm_domain;
+
+/* Density reservoir (Sec. 4; Sec. 3.4 prescribes densities at the inlet and
+ * outlet): cells with lo <= coordinate[axis] < hi have their pre-collision
+ * state reset to the rest equilibrium w_i*rho[s] of Eq. (Maxwell) every step,
+ * before the moments are taken. */
+typedef struct {
+    int32_t axis; /* 0: x, 1: y, 2: z */
+    int32_t lo, hi;
+    int32_t pad;
+    double rho[2];
+} lbm_reservoir;
+
+typedef struct {
+    int32_t ncomp;            /* 1 or 2 fluid components                               */
+    int32_t c_ns;             /* 1: one n_s field for all components; 2: one per component */
+    double tau[2];            /* relaxation times, > 0.5 (Eq. LGS; nu = (tau - 1/2)/3)  */
+    double G_inter;           /* G_inter,12 = G_inter,21 of Eq. (SC_F_inter)            */
+    double G_ads[2];          /* G_ads,sigma of Eq. (SC_F_ads)                          */
+    double F_ext[3];          /* external force density, split by Eq. (SC_F_ext)        */
+    double g_scale;           /* interaction stencils weight neighbours by g_scale*w_i;
+                                 1 is the paper's Eqs. (SC_F_inter), (SC_F_ads)          */
+    double rho_shift[2];      /* rho0_sigma of the shifted storage                      */
+    int32_t storage;          /* lbm_storage                                            */
+    int32_t store_scale_log2; /* power-of-two scale of stored values (16-bit formats)   */
+    int32_t n_res;            /* number of reservoirs, 0..LBM_MAX_RES                   */
+    int32_t check_every;      /* health check (finite mass) every k steps; 0 = never    */
+    lbm_reservoir res[LBM_MAX_RES];
+} lbm_params;
+
+/* Device memory a context needs, for callers that allocate it themselves. */
+typedef struct {
+    uint64_t pop_bytes;     /* each of the two population buffers            */
+    uint64_t ns_bytes;      /* bounce-back fractions (float32, c_ns*N)        */
+    uint64_t scratch_bytes; /* moments, checkpoint staging and reductions     */
+} lbm_sizes;
+
+/* Caller-provided device buffers (e.g. from PyTorch).  All four must be given,
+ * 256-byte aligned, of at least the sizes of lbm_required_bytes, and must
+ * outlive the context.  The library never frees them. */
+typedef struct {
+    void* f_a;
+    void* f_b;
+    void* n_s;
+    void* scratch;
+} lbm_device_buffers;
+
+typedef struct {
+    double mass[2];     /* sum over cells of rho_sigma (Eq. rho_BGK), FP64      */
+    double momentum[3]; /* sum over cells of rho*u_macro (Eq. HMCSC_u_macro)    */
+    int64_t time;       /* time step t of the state the totals describe         */
+    int32_t finite;     /* 1 if every mass and momentum total is finite         */
+    int32_t pad;
+} lbm_totals;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Size of each device buffer for the domain and parameters.  LBM_EINVAL when the
+ * parameters are rejected (same rules as lbm_create). */
+int lbm_required_bytes(const lbm_domain* dom, const lbm_params* prm, lbm_sizes* out);
+
+/* Create a simulation and initialise it at t = 0 to the rest equilibrium
+ * f_i = w_i*rho_init[s*N + n] (u = 0) of Eq. (Maxwell); reservoir cells start at
+ * their prescribed densities.
+ *   n_s      float32 host array [c_ns][N], every value in [0, 1] (Eq. LGS).
+ *   rho_init FP64 host array [ncomp][N], finite.
+ *   bufs     caller device buffers, or NULL: the library allocates and frees them.
+ *   stream   hipStream_t to queue all work on, or NULL for the default stream.
+ * Rejects ncomp/c_ns outside {1,2} (c_ns <= ncomp), tau <= 0.5, n_s outside
+ * [0,1], empty or over-large domains, bad reservoirs or storage (LBM_EINVAL).
+ * *out is NULL on failure.  Returns after the initial state is queued. */
+int lbm_create(const lbm_domain* dom, const float* n_s, const double* rho_init,
+               const lbm_params* prm, const lbm_device_buffers* bufs, void* stream,
+               lbm_ctx** out);
+
+/* Advance nsteps >= 0 time steps, asynchronously on the context stream.  When
+ * check_every > 0 the FP64 totals are checked every check_every steps (this
+ * synchronises) and LBM_EUNSTABLE is returned, with the time of the failing
+ * check kept, if they are not finite. */
+int lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Macroscopic fields at the current time t, from the pre-collision state,
+ * computed on the device in FP64 and copied to caller-owned host arrays (any
+ * pointer may be NULL):
+ *   rho [ncomp][N]  rho_sigma, Eq. (rho_BGK)
+ *   u   [3][N]      u_macro, Eq. (HMCSC_u_macro), with F_tot of Sec. 2
+ *   p   [N]         p = (rho + g_scale*G_inter*rho_1*rho_2)/3, Eq. (SC_pressure)
+ *   tot             FP64 totals (lbm_totals)
+ * Synchronises the context stream. */
+int lbm_moments(lbm_ctx* ctx, double* rho, double* u, double* p, lbm_totals* tot);
+
+/* FP64 totals only (no per-cell copy-back).  Synchronises. */
+int lbm_totals_get(lbm_ctx* ctx, lbm_totals* tot);
+
+/* Canonical populations (see above) of the current state into f [ncomp*19*N].
+ * Reservoir cells hold their prescribed equilibrium.  Synchronises. */
+int lbm_get_populations(lbm_ctx* ctx, double* f);
+
+/* Replace the state by canonical populations f [ncomp*19*N] (rounded to the
+ * storage format).  The time counter is kept.  Synchronises. */
+int lbm_set_populations(lbm_ctx* ctx, const double* f);
+
+/* Change the prescribed densities of reservoir r (e.g. a rising inlet density,
+ * Sec. 4) from the next step on. */
+int lbm_set_reservoir(lbm_ctx* ctx, int32_t r, const double rho[2]);
+
+/* Current time step t (number of steps applied since creation). */
+int64_t lbm_time(const lbm_ctx* ctx);
+
+/* Block until all queued work of the context is done. */
+int lbm_sync(lbm_ctx* ctx);
+
+/* Average device time in milliseconds of the step kernel launches of the last
+ * lbm_step call, measured with HIP events on the context stream (0 if none). */
+double lbm_last_step_ms(const lbm_ctx* ctx);
+
+/* Free library-owned memory (bound buffers are left alone).  Synchronises.
+ * NULL is ignored. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Static text for an LBM_E* code. */
+const char* lbm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -65,7 +65,7 @@ class Setup:
     G: float = 0.0
     G_ads: Sequence[float] = (0.0, 0.0)
     F_ext: Sequence[float] = (0.0, 0.0, 0.0)
-    g_scale: float = 3.0
+    g_scale: float = 1.0
     lattice: int = 19
     reservoirs: list = field(default_factory=list)
     nthreads: int = 0

@@ -1,0 +1,74 @@
+// Internal interface between the host runtime and the HIP kernels of the HMCSC
+// library.  Not part of the public ABI (that is include/lbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hm {
+
+constexpr int kQ = 19;
+constexpr int kMaxRes = 4;
+constexpr int kTileX = 64;  // cells per tile row: one wavefront
+
+enum Storage { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
+
+// Everything a launch needs besides the buffers, in double precision; the
+// launchers convert to the arithmetic type of the storage format.
+struct Problem {
+    int nx, ny, nz;
+    int64_t N;
+    int ncomp, c_ns;
+    int storage;
+    double tau[2];
+    double G_s;        // G_inter * g_scale
+    double Gads_s[2];  // G_ads * g_scale
+    double F[3];
+    double rho0[2];
+    double scale;      // 2^store_scale_log2
+    double g_scale, G_inter;
+    int n_res;
+    int res_axis[kMaxRes], res_lo[kMaxRes], res_hi[kMaxRes];
+    double res_rho[kMaxRes][2];
+};
+
+struct Launch {
+    int tile_y;   // rows per tile (4 or 8)
+    int zchunk;   // planes per block
+};
+
+// Bytes per stored population.
+int storage_bytes(int storage);
+
+// One time step A -> B (pull streaming, fused forces/collision/bounce-back).
+hipError_t launch_step(const Problem& p, const Launch& l, const void* A, void* B,
+                       const float* ns, hipStream_t s);
+
+// t = 0 state: rest equilibrium of rho_init (device FP64 [ncomp][N]).
+hipError_t launch_init(const Problem& p, const double* rho_init, void* A, hipStream_t s);
+
+// Canonical FP64 pre-collision populations of component/direction (s, i)
+// into out[N] (pull + decode + reservoir reset).
+hipError_t launch_canonical(const Problem& p, const void* A, int s, int i, double* out,
+                            hipStream_t st);
+
+// Store canonical FP64 populations of (s, i) from in[N] into A.
+hipError_t launch_set_canonical(const Problem& p, const double* in, int s, int i, void* A,
+                                hipStream_t st);
+
+// FP64 densities rho[s*N + n] of the current state.
+hipError_t launch_density(const Problem& p, const void* A, double* rho, hipStream_t st);
+
+// FP64 moments from the state and its densities; per-block partial totals
+// (mass[2], momentum[3]) to partials[nblocks*5]; fields optional (NULL).
+// Returns the number of blocks used in *nblocks.
+hipError_t launch_moments(const Problem& p, const void* A, const float* ns, const double* rho,
+                          double* u, double* pr, double* partials, int* nblocks,
+                          hipStream_t st);
+
+// Deterministic sum of nblocks partials (5 doubles each) into out[5].
+hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
+
+int moments_max_blocks();
+
+}  // namespace hm

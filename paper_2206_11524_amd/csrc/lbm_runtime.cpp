@@ -1,0 +1,404 @@
+// Host runtime of the HMCSC library: the C ABI of include/lbm.h on top of the
+// HIP kernels.  One context = one periodic D3Q19 domain on one device, its two
+// population buffers (A -> B, swapped every step), the n_s field, and a scratch
+// area for FP64 diagnostics and checkpoint staging.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm_kernels.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Scratch layout: [rho ncomp*N][u 3N][p N][partials][totals 5] (FP64).
+struct ScratchLayout {
+    size_t rho, u, p, partials, totals, bytes;
+};
+
+ScratchLayout scratch_layout(int64_t N, int ncomp)
+{
+    ScratchLayout s{};
+    size_t off = 0;
+    s.rho = off; off = align_up(off + sizeof(double) * static_cast<size_t>(ncomp) * N);
+    s.u = off; off = align_up(off + sizeof(double) * 3 * static_cast<size_t>(N));
+    s.p = off; off = align_up(off + sizeof(double) * static_cast<size_t>(N));
+    s.partials = off; off = align_up(off + sizeof(double) * 5 * hm::moments_max_blocks());
+    s.totals = off; off = align_up(off + sizeof(double) * 5);
+    s.bytes = off;
+    return s;
+}
+
+int validate(const lbm_domain* d, const lbm_params* p)
+{
+    if (!d || !p) return LBM_EINVAL;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return LBM_EINVAL;
+    const int64_t N = static_cast<int64_t>(d->nx) * d->ny * d->nz;
+    if (N >= (int64_t(1) << 31)) return LBM_EINVAL;
+    if (p->ncomp < 1 || p->ncomp > 2) return LBM_EINVAL;
+    if (p->c_ns < 1 || p->c_ns > 2 || p->c_ns > p->ncomp) return LBM_EINVAL;
+    for (int s = 0; s < p->ncomp; ++s) {
+        if (!(p->tau[s] > 0.5) || !std::isfinite(p->tau[s])) return LBM_EINVAL;
+        if (!std::isfinite(p->G_ads[s]) || !std::isfinite(p->rho_shift[s])) return LBM_EINVAL;
+    }
+    if (!std::isfinite(p->G_inter) || !std::isfinite(p->g_scale)) return LBM_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->F_ext[a])) return LBM_EINVAL;
+    if (p->storage < LBM_F64 || p->storage > LBM_BF16S) return LBM_EINVAL;
+    if (p->store_scale_log2 < -30 || p->store_scale_log2 > 30) return LBM_EINVAL;
+    if ((p->storage == LBM_F64 || p->storage == LBM_F32) && p->store_scale_log2 != 0) return LBM_EINVAL;
+    if (p->n_res < 0 || p->n_res > LBM_MAX_RES) return LBM_EINVAL;
+    const int dims[3] = {d->nx, d->ny, d->nz};
+    for (int r = 0; r < p->n_res; ++r) {
+        const lbm_reservoir& R = p->res[r];
+        if (R.axis < 0 || R.axis > 2 || R.lo < 0 || R.hi < R.lo || R.hi > dims[R.axis]) return LBM_EINVAL;
+        for (int s = 0; s < p->ncomp; ++s)
+            if (!std::isfinite(R.rho[s])) return LBM_EINVAL;
+    }
+    if (p->check_every < 0) return LBM_EINVAL;
+    return LBM_OK;
+}
+
+hm::Problem make_problem(const lbm_domain* d, const lbm_params* p)
+{
+    hm::Problem q{};
+    q.nx = d->nx; q.ny = d->ny; q.nz = d->nz;
+    q.N = static_cast<int64_t>(d->nx) * d->ny * d->nz;
+    q.ncomp = p->ncomp; q.c_ns = p->c_ns; q.storage = p->storage;
+    for (int s = 0; s < 2; ++s) {
+        q.tau[s] = s < p->ncomp ? p->tau[s] : 1.0;
+        q.Gads_s[s] = s < p->ncomp ? p->G_ads[s] * p->g_scale : 0.0;
+        q.rho0[s] = s < p->ncomp ? p->rho_shift[s] : 0.0;
+    }
+    q.G_s = p->G_inter * p->g_scale;
+    q.g_scale = p->g_scale;
+    q.G_inter = p->G_inter;
+    for (int a = 0; a < 3; ++a) q.F[a] = p->F_ext[a];
+    q.scale = std::ldexp(1.0, p->store_scale_log2);
+    q.n_res = p->n_res;
+    for (int r = 0; r < hm::kMaxRes; ++r) {
+        if (r < p->n_res) {
+            q.res_axis[r] = p->res[r].axis; q.res_lo[r] = p->res[r].lo; q.res_hi[r] = p->res[r].hi;
+            q.res_rho[r][0] = p->res[r].rho[0];
+            q.res_rho[r][1] = p->ncomp == 2 ? p->res[r].rho[1] : 0.0;
+        } else {
+            q.res_axis[r] = 0; q.res_lo[r] = 0; q.res_hi[r] = 0;
+            q.res_rho[r][0] = q.res_rho[r][1] = 0.0;
+        }
+    }
+    return q;
+}
+
+int env_int(const char* name, int dflt)
+{
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
+hm::Launch choose_launch(const hm::Problem& p)
+{
+    hm::Launch l{};
+    // FP64 with two components needs the smaller tile to stay within the
+    // register file (no spills)
+    const bool wide = p.storage == hm::kF64 && p.ncomp == 2;
+    l.tile_y = env_int("LBM_TILE_Y", (p.ny >= 8 && !wide) ? 8 : 4);
+    if (l.tile_y != 4 && l.tile_y != 8) l.tile_y = 8;
+    const int ntx = (p.nx + hm::kTileX - 1) / hm::kTileX;
+    const int nty = (p.ny + l.tile_y - 1) / l.tile_y;
+    const int64_t cols = static_cast<int64_t>(ntx) * nty;
+    int zc = env_int("LBM_ZCHUNK", 0);
+    if (zc <= 0) {
+        // aim at >= 1024 blocks, but keep the z-halo (2 planes per chunk) small
+        const int64_t want_chunks = std::max<int64_t>(1, (1024 + cols - 1) / cols);
+        zc = static_cast<int>(std::max<int64_t>(16, (p.nz + want_chunks - 1) / want_chunks));
+    }
+    l.zchunk = std::min(std::max(zc, 1), p.nz);
+    return l;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_domain dom;
+    lbm_params prm;
+    hm::Problem prob;
+    hm::Launch launch;
+    lbm_sizes sizes;
+    ScratchLayout sl;
+    void* buf[2];
+    float* ns;
+    char* scratch;
+    bool owned;
+    hipStream_t stream;
+    int device;
+    int cur;  // index of the buffer holding the current state
+    int64_t t;
+    hipEvent_t ev0, ev1;
+    int64_t timed_steps;
+};
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        if ((expr) != hipSuccess) return LBM_EDEVICE;  \
+    } while (0)
+
+extern "C" {
+
+const char* lbm_strerror(int code)
+{
+    switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory";
+    case LBM_EDEVICE: return "HIP device error";
+    case LBM_EUNSTABLE: return "non-finite state (unstable simulation)";
+    case LBM_ENOTFOUND: return "unknown ticket";
+    case LBM_EAGAIN: return "not ready";
+    default: return "unknown error";
+    }
+}
+
+int lbm_required_bytes(const lbm_domain* d, const lbm_params* p, lbm_sizes* out)
+{
+    const int rc = validate(d, p);
+    if (rc) return rc;
+    if (!out) return LBM_EINVAL;
+    const int64_t N = static_cast<int64_t>(d->nx) * d->ny * d->nz;
+    out->pop_bytes = align_up(static_cast<size_t>(hm::storage_bytes(p->storage)) * hm::kQ * p->ncomp * N);
+    out->ns_bytes = align_up(sizeof(float) * static_cast<size_t>(p->c_ns) * N);
+    out->scratch_bytes = scratch_layout(N, p->ncomp).bytes;
+    return LBM_OK;
+}
+
+static void free_owned(lbm_ctx* c)
+{
+    if (!c->owned) return;
+    if (c->buf[0]) (void)hipFree(c->buf[0]);
+    if (c->buf[1]) (void)hipFree(c->buf[1]);
+    if (c->ns) (void)hipFree(c->ns);
+    if (c->scratch) (void)hipFree(c->scratch);
+    c->buf[0] = c->buf[1] = nullptr;
+    c->ns = nullptr;
+    c->scratch = nullptr;
+}
+
+void lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_owned(c);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+int lbm_create(const lbm_domain* dom, const float* n_s, const double* rho_init, const lbm_params* prm,
+               const lbm_device_buffers* bufs, void* stream, lbm_ctx** out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    int rc = validate(dom, prm);
+    if (rc) return rc;
+    if (!n_s || !rho_init) return LBM_EINVAL;
+    const int64_t N = static_cast<int64_t>(dom->nx) * dom->ny * dom->nz;
+    for (int64_t k = 0; k < static_cast<int64_t>(prm->c_ns) * N; ++k)
+        if (!(n_s[k] >= 0.0f && n_s[k] <= 1.0f)) return LBM_EINVAL;
+    for (int64_t k = 0; k < static_cast<int64_t>(prm->ncomp) * N; ++k)
+        if (!std::isfinite(rho_init[k])) return LBM_EINVAL;
+    if (bufs && (!bufs->f_a || !bufs->f_b || !bufs->n_s || !bufs->scratch)) return LBM_EINVAL;
+    if (bufs) {
+        const void* ps[4] = {bufs->f_a, bufs->f_b, bufs->n_s, bufs->scratch};
+        for (const void* q : ps)
+            if (reinterpret_cast<uintptr_t>(q) % kAlign) return LBM_EINVAL;
+    }
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    c->dom = *dom;
+    c->prm = *prm;
+    c->prob = make_problem(dom, prm);
+    c->launch = choose_launch(c->prob);
+    lbm_required_bytes(dom, prm, &c->sizes);
+    c->sl = scratch_layout(N, prm->ncomp);
+    c->stream = static_cast<hipStream_t>(stream);
+    c->cur = 0;
+    c->t = 0;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LBM_EDEVICE; }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_EDEVICE;
+    }
+    if (bufs) {
+        c->owned = false;
+        c->buf[0] = bufs->f_a;
+        c->buf[1] = bufs->f_b;
+        c->ns = static_cast<float*>(bufs->n_s);
+        c->scratch = static_cast<char*>(bufs->scratch);
+    } else {
+        c->owned = true;
+        if (hipMalloc(&c->buf[0], c->sizes.pop_bytes) != hipSuccess ||
+            hipMalloc(&c->buf[1], c->sizes.pop_bytes) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&c->ns), c->sizes.ns_bytes) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&c->scratch), c->sizes.scratch_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            lbm_destroy(c);
+            return LBM_ENOMEM;
+        }
+    }
+    // n_s and the initial densities; the densities are staged in the rho slot of scratch
+    double* rho_dev = reinterpret_cast<double*>(c->scratch + c->sl.rho);
+    if (hipMemcpyAsync(c->ns, n_s, sizeof(float) * prm->c_ns * N, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(rho_dev, rho_init, sizeof(double) * prm->ncomp * N, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hm::launch_init(c->prob, rho_dev, c->buf[0], c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_EDEVICE;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+static int compute_totals(lbm_ctx* c, bool fields, lbm_totals* tot)
+{
+    double* rho = reinterpret_cast<double*>(c->scratch + c->sl.rho);
+    double* u = reinterpret_cast<double*>(c->scratch + c->sl.u);
+    double* p = reinterpret_cast<double*>(c->scratch + c->sl.p);
+    double* part = reinterpret_cast<double*>(c->scratch + c->sl.partials);
+    double* tots = reinterpret_cast<double*>(c->scratch + c->sl.totals);
+    int nb = 0;
+    HIP_TRY(hm::launch_density(c->prob, c->buf[c->cur], rho, c->stream));
+    HIP_TRY(hm::launch_moments(c->prob, c->buf[c->cur], c->ns, rho, fields ? u : nullptr, fields ? p : nullptr,
+                               part, &nb, c->stream));
+    HIP_TRY(hm::launch_reduce(part, nb, tots, c->stream));
+    double h[5];
+    HIP_TRY(hipMemcpyAsync(h, tots, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (tot) {
+        tot->mass[0] = h[0];
+        tot->mass[1] = c->prm.ncomp == 2 ? h[1] : 0.0;
+        for (int a = 0; a < 3; ++a) tot->momentum[a] = h[2 + a];
+        tot->time = c->t;
+        int fin = 1;
+        for (double v : h) fin &= std::isfinite(v) ? 1 : 0;
+        tot->finite = fin;
+        tot->pad = 0;
+    }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return LBM_EINVAL;
+    if (nsteps == 0) return LBM_OK;
+    HIP_TRY(hipEventRecord(c->ev0, c->stream));
+    for (int64_t k = 0; k < nsteps; ++k) {
+        HIP_TRY(hm::launch_step(c->prob, c->launch, c->buf[c->cur], c->buf[1 - c->cur], c->ns, c->stream));
+        c->cur = 1 - c->cur;
+        c->t += 1;
+        if (c->prm.check_every > 0 && c->t % c->prm.check_every == 0) {
+            lbm_totals tt;
+            const int rc = compute_totals(c, false, &tt);
+            if (rc) return rc;
+            if (!tt.finite) return LBM_EUNSTABLE;
+        }
+    }
+    HIP_TRY(hipEventRecord(c->ev1, c->stream));
+    c->timed_steps = nsteps;
+    return LBM_OK;
+}
+
+double lbm_last_step_ms(const lbm_ctx* c)
+{
+    if (!c || c->timed_steps <= 0) return 0.0;
+    if (hipEventSynchronize(c->ev1) != hipSuccess) return 0.0;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) return 0.0;
+    return static_cast<double>(ms) / static_cast<double>(c->timed_steps);
+}
+
+int lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, lbm_totals* tot)
+{
+    if (!c) return LBM_EINVAL;
+    const bool fields = rho || u || p;
+    const int rc = compute_totals(c, fields, tot);
+    if (rc) return rc;
+    const int64_t N = c->prob.N;
+    if (rho)
+        HIP_TRY(hipMemcpy(rho, c->scratch + c->sl.rho, sizeof(double) * c->prm.ncomp * N, hipMemcpyDeviceToHost));
+    if (u) HIP_TRY(hipMemcpy(u, c->scratch + c->sl.u, sizeof(double) * 3 * N, hipMemcpyDeviceToHost));
+    if (p) HIP_TRY(hipMemcpy(p, c->scratch + c->sl.p, sizeof(double) * N, hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+int lbm_totals_get(lbm_ctx* c, lbm_totals* tot)
+{
+    if (!c || !tot) return LBM_EINVAL;
+    return compute_totals(c, false, tot);
+}
+
+int lbm_get_populations(lbm_ctx* c, double* f)
+{
+    if (!c || !f) return LBM_EINVAL;
+    const int64_t N = c->prob.N;
+    double* stage = reinterpret_cast<double*>(c->scratch + c->sl.u);  // N doubles (u slot holds 3N)
+    for (int s = 0; s < c->prm.ncomp; ++s)
+        for (int i = 0; i < hm::kQ; ++i) {
+            HIP_TRY(hm::launch_canonical(c->prob, c->buf[c->cur], s, i, stage, c->stream));
+            HIP_TRY(hipMemcpyAsync(f + static_cast<size_t>(s * hm::kQ + i) * N, stage, sizeof(double) * N,
+                                   hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx* c, const double* f)
+{
+    if (!c || !f) return LBM_EINVAL;
+    const int64_t N = c->prob.N;
+    for (int64_t k = 0; k < static_cast<int64_t>(c->prm.ncomp) * hm::kQ * N; ++k)
+        if (!std::isfinite(f[k])) return LBM_EINVAL;
+    double* stage = reinterpret_cast<double*>(c->scratch + c->sl.u);
+    for (int s = 0; s < c->prm.ncomp; ++s)
+        for (int i = 0; i < hm::kQ; ++i) {
+            HIP_TRY(hipMemcpyAsync(stage, f + static_cast<size_t>(s * hm::kQ + i) * N, sizeof(double) * N,
+                                   hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hm::launch_set_canonical(c->prob, stage, s, i, c->buf[c->cur], c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+    return LBM_OK;
+}
+
+int lbm_set_reservoir(lbm_ctx* c, int32_t r, const double rho[2])
+{
+    if (!c || !rho || r < 0 || r >= c->prm.n_res) return LBM_EINVAL;
+    for (int s = 0; s < c->prm.ncomp; ++s)
+        if (!std::isfinite(rho[s])) return LBM_EINVAL;
+    for (int s = 0; s < c->prm.ncomp; ++s) {
+        c->prm.res[r].rho[s] = rho[s];
+        c->prob.res_rho[r][s] = rho[s];
+    }
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+int lbm_sync(lbm_ctx* c)
+{
+    if (!c) return LBM_EINVAL;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+}  // extern "C"

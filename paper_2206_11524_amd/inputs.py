@@ -7,6 +7,13 @@ the GPU library and the CPU checker consume these arrays unchanged.
 
 Random numbers come from ``numpy.random.Generator(PCG64(seed))``.
 
+Interaction strengths: the droplet, electrode and porous-domain workloads quote
+G_inter = 0.9 and G_ads = +-0.1 / +-0.3 in the normalisation where the
+interaction stencil weights sum to sum_i W_i c_i c_i = I (W_i = 3 w_i), common for
+multi-component Shan-Chen set-ups; they therefore carry ``g_scale = 3``.  With
+the paper's literal stencil (g_scale = 1) G_inter = 0.9 at these densities lies
+below the demixing threshold and a droplet dissolves.
+
 Workloads (the paper's own 3-D microstructure and separator images are not
 available, these synthetic stand-ins have the same structure):
 
@@ -38,7 +45,7 @@ class Workload:
     G: float = 0.0
     G_ads: tuple = (0.0, 0.0)
     F_ext: tuple = (0.0, 0.0, 0.0)
-    g_scale: float = 3.0
+    g_scale: float = 1.0
     reservoirs: list = field(default_factory=list)  # [(axis, lo, hi, (rho_1, rho_2))]
     name: str = ""
 
@@ -88,7 +95,7 @@ def droplet(n=32, radius=8.0, ns_value=0.1, rho_in=1.0, rho_out=0.03, noise=1e-3
     if noise:
         r += rng(seed).uniform(-noise, noise, size=r.shape)
     ns = np.full((1, n, n, n), ns_value, np.float32)
-    return Workload((n, n, n), ns, r, ncomp=2, tau=(tau, tau), G=G, name=f"droplet{n}")
+    return Workload((n, n, n), ns, r, ncomp=2, tau=(tau, tau), G=G, g_scale=3.0, name=f"droplet{n}")
 
 
 def gray_channel(nx=64, ny=64, nz=128, slab=(24, 40), ns_slab=0.1, force=1e-6, tau=0.8) -> Workload:
@@ -175,7 +182,7 @@ def electrode(n=256, seed=2000, res_layers=16, solid_fraction=0.5, rmin=6.0, rma
     r[0, :zlo] = rho_main
     r[1, :zlo] = rho_dis
     res = [(2, 0, zlo, (rho_main, rho_dis)), (2, zhi, n, (rho_dis, rho_main))]
-    return Workload(shape, ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads),
+    return Workload(shape, ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads), g_scale=3.0,
                     reservoirs=res, name=f"electrode{n}")
 
 
@@ -199,5 +206,5 @@ def porous_domain(edge, seed, porosity=None, ns_max=0.9, G=0.9, G_ads=(0.1, -0.1
     quarter = max(1, n // 4)
     r[0, :quarter][~solid[:quarter]] = rho_main
     r[1, :quarter][~solid[:quarter]] = rho_dis
-    return Workload((n, n, n), ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads),
+    return Workload((n, n, n), ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads), g_scale=3.0,
                     F_ext=(0.0, 0.0, force), name=f"porous{n}_{seed}")

@@ -1,0 +1,112 @@
+"""The C ABI library loads and exports every function include/lbm.h declares,
+and its host-side validation and sizing behave as documented.  No compute call
+is made here (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2206_11524_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_\w+)\s*\(", text))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.fail("libhmcsc.so is not built (run python -m paper_2206_11524_amd.build)")
+    return lbm._lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 12
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    # and the binding covers all of them
+    assert names <= set(lbm.SIGNATURES) | set(getattr(lbm, "SERVE_SIGNATURES", {}))
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert lib.lbm_strerror(code)
+
+
+def test_required_bytes_matches_layout(lib):
+    for storage, b in (("f64", 8), ("f32", 4), ("f16s", 2), ("bf16s", 2)):
+        p = lbm.make_params(ncomp=2, c_ns=1, storage=storage)
+        s = lbm.required_bytes((256, 256, 256), p)
+        assert s.pop_bytes == 2 * 19 * 256 ** 3 * b
+        assert s.ns_bytes == 4 * 256 ** 3
+        assert s.scratch_bytes >= 8 * (2 + 3 + 1) * 256 ** 3
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ncomp=3), dict(ncomp=1, c_ns=2), dict(tau=(0.5, 1.0)), dict(tau=(1.0, 0.4)),
+    dict(storage=7), dict(storage="f32", store_scale_log2=3), dict(G=float("nan")),
+    dict(reservoirs=[(3, 0, 1, (1.0, 0.0))]), dict(reservoirs=[(2, 0, 99, (1.0, 0.0))]),
+    dict(check_every=-1),
+])
+def test_invalid_parameters_rejected_before_any_device_work(lib, bad):
+    p = lbm.make_params(**{**dict(ncomp=2, c_ns=1, tau=(1.0, 1.0)), **bad})
+    d = lbm.Domain(8, 8, 8)
+    s = lbm.Sizes()
+    assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_EINVAL
+    ns = np.zeros(8 ** 3, np.float32)
+    rho = np.ones(2 * 8 ** 3)
+    ctx = C.c_void_p(1)
+    rc = lib.lbm_create(C.byref(d), ns.ctypes.data, rho.ctypes.data, C.byref(p), None, None, C.byref(ctx))
+    assert rc == lbm.LBM_EINVAL
+    assert not ctx.value
+
+
+@pytest.mark.parametrize("shape", [(0, 4, 4), (4, -1, 4), (2048, 2048, 1024)])
+def test_bad_domains_rejected(lib, shape):
+    p = lbm.make_params()
+    d = lbm.Domain(*shape)
+    s = lbm.Sizes()
+    assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_EINVAL
+
+
+def test_bounce_back_fraction_outside_unit_interval_rejected(lib):
+    p = lbm.make_params()
+    d = lbm.Domain(4, 4, 4)
+    ns = np.zeros(64, np.float32)
+    ns[5] = 1.5
+    rho = np.ones(128)
+    ctx = C.c_void_p()
+    assert lib.lbm_create(C.byref(d), ns.ctypes.data, rho.ctypes.data, C.byref(p), None, None,
+                          C.byref(ctx)) == lbm.LBM_EINVAL
+    ns[5] = np.nan
+    assert lib.lbm_create(C.byref(d), ns.ctypes.data, rho.ctypes.data, C.byref(p), None, None,
+                          C.byref(ctx)) == lbm.LBM_EINVAL
+
+
+def test_misaligned_caller_buffers_rejected(lib):
+    p = lbm.make_params()
+    d = lbm.Domain(4, 4, 4)
+    ns = np.zeros(64, np.float32)
+    rho = np.ones(128)
+    bufs = lbm.DeviceBuffers(4096, 4096 + 8, 8192, 16384)
+    ctx = C.c_void_p()
+    assert lib.lbm_create(C.byref(d), ns.ctypes.data, rho.ctypes.data, C.byref(p), C.byref(bufs), None,
+                          C.byref(ctx)) == lbm.LBM_EINVAL
+
+
+def test_null_context_calls_are_rejected(lib):
+    assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_sync(None) == lbm.LBM_EINVAL
+    assert lib.lbm_time(None) == -1
+    lib.lbm_destroy(None)
