@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--variants", default="f32,f16s,bf16s")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB ten times (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -144,6 +146,16 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_each_way": n * 4, "launches": 10}))
+        return
 
     w = inputs.electrode(n=args.edge)
     variants = [v for v in args.variants.split(",") if v]

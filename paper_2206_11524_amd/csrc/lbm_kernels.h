@@ -9,7 +9,6 @@ namespace hm {
 
 constexpr int kQ = 19;
 constexpr int kMaxRes = 4;
-constexpr int kTileX = 64;  // cells per tile row: one wavefront
 
 enum Storage { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
@@ -33,9 +32,13 @@ struct Problem {
 };
 
 struct Launch {
-    int tile_y;   // rows per tile (4 or 8)
+    int tile_x;   // cells per tile row (32 or 64)
+    int tile_y;   // rows per tile (4, 8 or 16 with 32-wide rows)
     int zchunk;   // planes per block
 };
+
+// True if the tile shape is compiled in.
+bool tile_supported(int tile_x, int tile_y);
 
 // Bytes per stored population.
 int storage_bytes(int storage);

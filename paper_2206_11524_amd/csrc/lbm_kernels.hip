@@ -42,19 +42,59 @@ __host__ __device__ constexpr T wgt(int i)
 // ---------------------------------------------------------------------------
 // Storage formats.  decode() returns the shifted value h in the arithmetic
 // type T, encode() rounds h back (round to nearest even for 16-bit).
+// Buffer resources: raw (stride 0) descriptors whose range check turns any
+// access beyond num_records into a zero load / dropped store.  Stores of the
+// step are non-temporal (cache-policy bit NT): the next step reads them only
+// after the whole domain has streamed through the caches.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kNT = 2;  // cache policy: non-temporal
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0),
+                                             static_cast<int>(bytes), 0x00020000);
+}
+
 struct F64 {
     using E = double;
     using T = double;
     static __device__ __forceinline__ T dec(E v, T) { return v; }
     static __device__ __forceinline__ E enc(T v, T) { return v; }
+    static __device__ __forceinline__ E bld(rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void bst(E v, rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, kNT);
+    }
 };
 struct F32 {
     using E = float;
     using T = float;
     static __device__ __forceinline__ T dec(E v, T) { return v; }
     static __device__ __forceinline__ E enc(T v, T) { return v; }
+    static __device__ __forceinline__ E bld(rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void bst(E v, rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vo, so, kNT);
+    }
 };
-struct F16 {
+struct Half16 {
+    static __device__ __forceinline__ uint16_t bld(rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+    }
+    static __device__ __forceinline__ void bst(uint16_t v, rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(v, r, vo, so, kNT);
+    }
+};
+struct F16 : Half16 {
     using E = uint16_t;
     using T = float;
     static __device__ __forceinline__ T dec(E v, T inv_scale)
@@ -66,7 +106,7 @@ struct F16 {
         return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v * scale));
     }
 };
-struct BF16 {
+struct BF16 : Half16 {
     using E = uint16_t;
     using T = float;
     static __device__ __forceinline__ T dec(E v, T inv_scale)
@@ -157,58 +197,119 @@ __device__ __forceinline__ PullIdx pull_idx(int x, int y, int z, int nx, int ny,
     return q;
 }
 
+// Fused step kernel.
+//
+// Addressing: the pull source of direction i at cell (x, y, z) is the cell
+// (x - cx, y - cy, z - cz).  Its plane part is uniform across the block, so it
+// is folded into a per-direction base pointer computed on the scalar unit; the
+// in-plane part takes one of nine values per thread, computed once before the
+// z sweep.  Loads are therefore "uniform base + 32-bit lane offset".
+template <typename E>
+__device__ __forceinline__ E ld_off(const E* base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+template <typename E>
+__device__ __forceinline__ void st_off(E* base, uint32_t byte_off, E v)
+{
+    *reinterpret_cast<E*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// In-plane byte offsets of the nine (x - cx, y - cy) sources of a cell.
+struct PlaneOffs {
+    uint32_t o[3][3];  // [cy + 1][cx + 1]
+};
+
+template <typename E>
+__device__ __forceinline__ PlaneOffs plane_offs(int x, int y, int nx, int ny)
+{
+    const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // x - c, c = -1, 0, 1
+    const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    PlaneOffs q;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q.o[b][a] = static_cast<uint32_t>((ys[b] * nx + xs[a]) * static_cast<int>(sizeof(E)));
+    return q;
+}
+
 // Pull the shifted pre-collision populations of one cell and component.
+// r covers the 19 direction arrays of component s; soff[c + 1] is the byte
+// offset of the source plane z - c; q holds the in-plane byte offsets.
 template <typename ST, typename T>
-__device__ __forceinline__ void pull_cell(const typename ST::E* __restrict__ A, const Args<T>& a,
-                                          const PullIdx& q, int s, int res, T h[kQ])
+__device__ __forceinline__ void pull(rsrc_t r, uint32_t dir_bytes, const uint32_t soff[3], const PlaneOffs& q,
+                                     T inv_scale, T h[kQ])
 {
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const int src = q.pln[CZ[i] + 1] + q.row[CY[i] + 1] + q.col[CX[i] + 1];
-        const typename ST::E* Ai = A + static_cast<size_t>(s * kQ + i) * static_cast<size_t>(a.N);
-        h[i] = ST::dec(Ai[src], a.inv_scale);
-    }
-    if (res >= 0) {
-        const T dr = a.res_dr[res][s];
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) h[i] = wgt<T>(i) * dr;
-    }
+    for (int i = 0; i < kQ; ++i)
+        h[i] = ST::dec(ST::bld(r, q.o[CY[i] + 1][CX[i] + 1], soff[CZ[i] + 1] + static_cast<uint32_t>(i) * dir_bytes),
+                       inv_scale);
 }
 
 template <typename T>
 __device__ __forceinline__ T sum19(const T h[kQ])
 {
-    // pairwise order, fixed
     T acc = h[0];
 #pragma unroll
     for (int i = 1; i <= 9; ++i) acc += h[i] + h[i + 9];
     return acc;
 }
 
-// ---------------------------------------------------------------------------
-// Fused step kernel.
-template <typename ST, int NC, int CNS, int TY>
-struct StepKernel {
-    using T = typename ST::T;
-    using E = typename ST::E;
-    static constexpr int LW = kTileX + 2;       // LDS row width
-    static constexpr int LP = LW * (TY + 2);    // LDS plane size
-    static constexpr int NT = kTileX * TY;      // threads per block
-};
-
-template <typename ST, int NC, int CNS, int TY>
-__global__ __launch_bounds__(kTileX* TY) void k_step(Args<typename ST::T> a,
-                                                      const typename ST::E* __restrict__ A,
-                                                      typename ST::E* __restrict__ B,
-                                                      const float* __restrict__ ns)
+// sum_i sign(c_ia) v_i over the directions with c_ia != 0, paired i / i+9
+template <typename T, int AX>
+__device__ __forceinline__ T first_moment(const T h[kQ])
 {
-    using K = StepKernel<ST, NC, CNS, TY>;
+    T acc = T(0);
+#pragma unroll
+    for (int i = 1; i <= 9; ++i) {
+        const int c = AX == 0 ? CX[i] : (AX == 1 ? CY[i] : CZ[i]);
+        if (c) acc += c > 0 ? h[i] - h[i + 9] : h[i + 9] - h[i];
+    }
+    return acc;
+}
+
+// Neighbour stencil sum_i w_i phi(x + c_i) c_i read from an LDS plane triple.
+template <typename T, typename V, int LW>
+__device__ __forceinline__ void stencil(const V* pm, const V* p0, const V* pp, int me, T g[3])
+{
+    // group by weight: axis neighbours (1/18) and diagonals (1/36)
+    T ax[3] = {0, 0, 0}, dg[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        const V* pl = CZ[i] == 0 ? p0 : (CZ[i] > 0 ? pp : pm);
+        const T v = static_cast<T>(pl[me + CY[i] * LW + CX[i]]);
+        const bool axis = (CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]) == 1;
+        T* acc = axis ? ax : dg;
+        if (CX[i]) acc[0] += CX[i] > 0 ? v : -v;
+        if (CY[i]) acc[1] += CY[i] > 0 ? v : -v;
+        if (CZ[i]) acc[2] += CZ[i] > 0 ? v : -v;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[d] = ax[d] * (T(1) / T(18)) + dg[d] * (T(1) / T(36));
+}
+
+// One thread per (cell, component): a block of NC*TX*TY threads owns a TX x TY
+// column of cells; threads [s*TX*TY, (s+1)*TX*TY) handle component s.  The two
+// components of a cell meet only through LDS (densities and first moments),
+// which halves the registers per thread and doubles the waves per CU.
+template <typename ST, int NC, int CNS, int TX, int TY>
+__global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
+                                                          const typename ST::E* __restrict__ A,
+                                                          typename ST::E* __restrict__ B,
+                                                          const float* __restrict__ ns)
+{
     using T = typename ST::T;
     using E = typename ST::E;
-    constexpr int LW = K::LW, LP = K::LP, NT = K::NT;
+    constexpr int LW = TX + 2;
+    constexpr int LP = LW * (TY + 2);
+    constexpr int NTC = TX * TY;  // threads per component
+    constexpr int NT = NC * NTC;
+    constexpr int NSMAX = (LP + NT - 1) / NT;  // n_s cells staged per thread and plane
 
     __shared__ T s_rho[3][NC][LP];
     __shared__ float s_ns[3][CNS][LP];
+    __shared__ T s_j[NC][3][NTC];
 
     // XCD-aware tile order: blocks are dispatched round-robin over 8 XCDs, so
     // give each XCD a contiguous run of tiles (neighbours share its L2).
@@ -218,25 +319,30 @@ __global__ __launch_bounds__(kTileX* TY) void k_step(Args<typename ST::T> a,
     const int tx = L % a.ntx;
     const int ty = (L / a.ntx) % a.nty;
     const int tz = L / (a.ntx * a.nty);
-    const int x0 = tx * kTileX, y0 = ty * TY;
+    const int x0 = tx * TX, y0 = ty * TY;
     const int zs = tz * a.zchunk;
     const int ze = min(zs + a.zchunk, a.nz);
-    const int TXe = min(kTileX, a.nx - x0);
+    const int TXe = min(TX, a.nx - x0);
     const int TYe = min(TY, a.ny - y0);
+    const int plane = a.nx * a.ny;
 
-    const int lx = threadIdx.x % kTileX;
-    const int ly = threadIdx.x / kTileX;
+    const int s = NC == 1 ? 0 : static_cast<int>(threadIdx.x) / NTC;  // component of this thread
+    const int tl = static_cast<int>(threadIdx.x) - s * NTC;
+    const int lx = tl % TX;
+    const int ly = tl / TX;
     const bool act = lx < TXe && ly < TYe;
     const int x = x0 + min(lx, TXe - 1);
     const int y = y0 + min(ly, TYe - 1);
     const int me = (ly + 1) * LW + (lx + 1);
+    const PlaneOffs qme = plane_offs<E>(x, y, a.nx, a.ny);
+    const uint32_t own = static_cast<uint32_t>((y * a.nx + x) * static_cast<int>(sizeof(E)));
 
     // ring cell of this thread (if any): top row, bottom row, left, right column
     const int ring_n = 2 * (TXe + 2) + 2 * TYe;
-    int rlx = 0, rly = 0;
-    const bool ring = threadIdx.x < ring_n;
+    const bool ring = tl < ring_n;
+    int rlx, rly;
     {
-        const int r = threadIdx.x;
+        const int r = min(tl, ring_n - 1);
         if (r < TXe + 2) { rlx = r - 1; rly = -1; }
         else if (r < 2 * (TXe + 2)) { rlx = r - (TXe + 2) - 1; rly = TYe; }
         else if (r < 2 * (TXe + 2) + TYe) { rlx = -1; rly = r - 2 * (TXe + 2); }
@@ -245,165 +351,187 @@ __global__ __launch_bounds__(kTileX* TY) void k_step(Args<typename ST::T> a,
     const int rx = ((x0 + rlx) % a.nx + a.nx) % a.nx;
     const int ry = ((y0 + rly) % a.ny + a.ny) % a.ny;
     const int rme = (rly + 1) * LW + (rlx + 1);
+    const PlaneOffs qring = plane_offs<E>(rx, ry, a.nx, a.ny);
 
+    // n_s cells staged by this thread: LDS index and in-plane offset
     const int nsw = TXe + 2, nsh = TYe + 2;
-
-    // Densities of plane p into LDS slot: own cell from registers (h), ring cells pulled.
-    auto ring_density = [&](int p, int slot) {
-        if (ring) {
-            const PullIdx q = pull_idx(rx, ry, p, a.nx, a.ny, a.nz);
-            const int res = reservoir_of(a, rx, ry, p);
+    int ns_lds[NSMAX], ns_off[NSMAX];
 #pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                T hh[kQ];
-                pull_cell<ST, T>(A, a, q, s, res, hh);
-                s_rho[slot][s][rme] = a.rho0[s] + sum19(hh);
-            }
-        }
-    };
-    auto load_ns = [&](int p, int slot) {
-        const int plane = p * a.nx * a.ny;
-        for (int k = threadIdx.x; k < nsw * nsh; k += NT) {
-            const int llx = k % nsw - 1, lly = k / nsw - 1;
+    for (int k = 0; k < NSMAX; ++k) {
+        const int c = static_cast<int>(threadIdx.x) + k * NT;
+        if (c < nsw * nsh) {
+            const int llx = c % nsw - 1, lly = c / nsw - 1;
             const int gx = ((x0 + llx) % a.nx + a.nx) % a.nx;
             const int gy = ((y0 + lly) % a.ny + a.ny) % a.ny;
-#pragma unroll
-            for (int c = 0; c < CNS; ++c)
-                s_ns[slot][c][(lly + 1) * LW + llx + 1] = ns[static_cast<size_t>(c) * a.N + plane + gy * a.nx + gx];
+            ns_lds[k] = (lly + 1) * LW + llx + 1;
+            ns_off[k] = gy * a.nx + gx;
+        } else {
+            ns_lds[k] = -1;
+            ns_off[k] = 0;
         }
-    };
-    auto wrapz = [&](int p) { return p < 0 ? p + a.nz : (p >= a.nz ? p - a.nz : p); };
-
-    T cur[NC][kQ];
-    T nxt[NC][kQ];
-
-    // prologue: plane zs-1 (densities only) and plane zs (kept in cur)
-    {
-        const int pm = wrapz(zs - 1);
-        if (act) {
-            const PullIdx q = pull_idx(x, y, pm, a.nx, a.ny, a.nz);
-            const int res = reservoir_of(a, x, y, pm);
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                pull_cell<ST, T>(A, a, q, s, res, nxt[s]);
-                s_rho[0][s][me] = a.rho0[s] + sum19(nxt[s]);
-            }
-        }
-        ring_density(pm, 0);
-        load_ns(pm, 0);
-        if (act) {
-            const PullIdx q = pull_idx(x, y, zs, a.nx, a.ny, a.nz);
-            const int res = reservoir_of(a, x, y, zs);
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                pull_cell<ST, T>(A, a, q, s, res, cur[s]);
-                s_rho[1][s][me] = a.rho0[s] + sum19(cur[s]);
-            }
-        }
-        ring_density(zs, 1);
-        load_ns(zs, 1);
     }
 
-    int sm = 0, s0 = 1, sp = 2;  // LDS slots of planes z-1, z, z+1
-    for (int z = zs; z < ze; ++z) {
-        const int pn = wrapz(z + 1);
-        if (act) {
-            const PullIdx q = pull_idx(x, y, pn, a.nx, a.ny, a.nz);
-            const int res = reservoir_of(a, x, y, pn);
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                pull_cell<ST, T>(A, a, q, s, res, nxt[s]);
-                s_rho[sp][s][me] = a.rho0[s] + sum19(nxt[s]);
-            }
-        }
-        ring_density(pn, sp);
-        load_ns(pn, sp);
-        __syncthreads();
+    auto wrapz = [&](int p) { return p < 0 ? p + a.nz : (p >= a.nz ? p - a.nz : p); };
 
-        if (act) {
-            const int slot_of[3] = {sp, s0, sm};  // by 1 - c_z ... index with dz+1 below
-            (void)slot_of;
-            // moments
-            T rho_s[NC], j[NC][3];
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                rho_s[s] = a.rho0[s] + sum19(cur[s]);
-                T jx = 0, jy = 0, jz = 0;
-#pragma unroll
-                for (int i = 1; i < kQ; ++i) {
-                    if (CX[i]) jx += CX[i] > 0 ? cur[s][i] : -cur[s][i];
-                    if (CY[i]) jy += CY[i] > 0 ? cur[s][i] : -cur[s][i];
-                    if (CZ[i]) jz += CZ[i] > 0 ? cur[s][i] : -cur[s][i];
-                }
-                j[s][0] = jx; j[s][1] = jy; j[s][2] = jz;
-            }
-            T rho = 0, den = 0, num[3] = {0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                rho += rho_s[s];
-                den += rho_s[s] * a.inv_tau[s];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) num[d] += j[s][d] * a.inv_tau[s];
-            }
-            T up[3];
-            const T inv_den = den > T(0) ? T(1) / den : T(0);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) up[d] = num[d] * inv_den;
-            const T inv_rho = rho > T(0) ? T(1) / rho : T(0);
+    const uint32_t dir_bytes = static_cast<uint32_t>(a.N * static_cast<int>(sizeof(E)));
+    const uint32_t plane_bytes = static_cast<uint32_t>(plane * static_cast<int>(sizeof(E)));
+    // one buffer descriptor per component spans its 19 direction arrays
+    const uint32_t comp_bytes = static_cast<uint32_t>(kQ) * dir_bytes;
+    const rsrc_t ra = make_rsrc(A + static_cast<size_t>(s * kQ) * static_cast<size_t>(a.N), comp_bytes);
+    const rsrc_t rb = make_rsrc(B + static_cast<size_t>(s * kQ) * static_cast<size_t>(a.N), comp_bytes);
 
+    auto pull_plane = [&](int p, const PlaneOffs& q, T h[kQ]) {
+        const uint32_t so[3] = {static_cast<uint32_t>(wrapz(p + 1)) * plane_bytes,  // c_z = -1
+                                static_cast<uint32_t>(p) * plane_bytes,
+                                static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};  // c_z = +1
+        pull<ST, T>(ra, dir_bytes, so, q, a.inv_scale, h);
+    };
+    auto reservoir_override = [&](int res, T h[kQ]) {
+        if (res >= 0) {
+            const T dr = a.res_dr[res][s];
 #pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                // neighbour stencils sum_i w_i phi(x + c_i) c_i from LDS
-                T gi[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
-                const int cn = CNS == 2 ? s : 0;
-#pragma unroll
-                for (int i = 1; i < kQ; ++i) {
-                    const int slot = CZ[i] == 0 ? s0 : (CZ[i] > 0 ? sp : sm);
-                    const int k = me + CY[i] * LW + CX[i];
-                    const T wi = wgt<T>(i);
-                    if (NC == 2) {
-                        const T r = s_rho[slot][1 - s][k] * wi;
-                        if (CX[i]) gi[0] += CX[i] > 0 ? r : -r;
-                        if (CY[i]) gi[1] += CY[i] > 0 ? r : -r;
-                        if (CZ[i]) gi[2] += CZ[i] > 0 ? r : -r;
-                    }
-                    const T v = static_cast<T>(s_ns[slot][cn][k]) * wi;
-                    if (CX[i]) ga[0] += CX[i] > 0 ? v : -v;
-                    if (CY[i]) ga[1] += CY[i] > 0 ? v : -v;
-                    if (CZ[i]) ga[2] += CZ[i] > 0 ? v : -v;
-                }
-                // force per unit density: F_tot,s / rho_s of Eqs. (SC_F_inter),
-                // (SC_F_ads), (SC_F_ext); no shift for an absent component
-                T ueq[3];
-                const bool present = rho_s[s] > T(0);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const T acc = -a.G_s * gi[d] - a.Gads_s[s] * ga[d] + a.F[d] * inv_rho;
-                    ueq[d] = up[d] + (present ? a.tau[s] * acc : T(0));
-                }
-                const T uu = ueq[0] * ueq[0] + ueq[1] * ueq[1] + ueq[2] * ueq[2];
-                const T n = static_cast<T>(s_ns[s0][cn][me]);
-                const T omn = T(1) - n;
-                const T drho = rho_s[s] - a.rho0[s];
-                E* Bs = B + static_cast<size_t>(s * kQ) * static_cast<size_t>(a.N);
-                const int dst = (z * a.ny + y) * a.nx + x;
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    const T cu = T(CX[i]) * ueq[0] + T(CY[i]) * ueq[1] + T(CZ[i]) * ueq[2];
-                    const T heq = wgt<T>(i) * (drho + rho_s[s] * (cu * (T(3) + T(4.5) * cu) - T(1.5) * uu));
-                    const T h = cur[s][i];
-                    const T post = omn * (h - (h - heq) * a.inv_tau[s]) + n * cur[s][opp(i)];
-                    Bs[static_cast<size_t>(i) * static_cast<size_t>(a.N) + dst] = ST::enc(post, a.scale);
-                }
-            }
+            for (int i = 0; i < kQ; ++i) h[i] = wgt<T>(i) * dr;
         }
+    };
+    // densities of plane p: own cell into h, ring cell pulled here; n_s plane
+    auto stage_plane = [&](int p, int slot, T h[kQ]) {
+        if (act) {
+            pull_plane(p, qme, h);
+            reservoir_override(reservoir_of(a, x, y, p), h);
+            s_rho[slot][s][me] = a.rho0[s] + sum19(h);
+        }
+        if (ring) {
+            T hr[kQ];
+            pull_plane(p, qring, hr);
+            reservoir_override(reservoir_of(a, rx, ry, p), hr);
+            s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
+        }
+        const float* nsp = ns + static_cast<size_t>(p) * plane;
 #pragma unroll
-        for (int s = 0; s < NC; ++s)
+        for (int k = 0; k < NSMAX; ++k)
+            if (ns_lds[k] >= 0)
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) cur[s][i] = nxt[s][i];
-        const int t = sm;
-        sm = s0; s0 = sp; sp = t;
+                for (int c = 0; c < CNS; ++c) s_ns[slot][c][ns_lds[k]] = nsp[static_cast<size_t>(c) * a.N + ns_off[k]];
+    };
+    // first moment of the cell's component, published for the partner thread
+    auto publish_j = [&](const T h[kQ]) {
+        if (act && NC == 2) {
+            s_j[s][0][tl] = first_moment<T, 0>(h);
+            s_j[s][1][tl] = first_moment<T, 1>(h);
+            s_j[s][2][tl] = first_moment<T, 2>(h);
+        }
+    };
+
+    // Collision of plane z of this thread's component from h (pre-collision,
+    // shifted) and the LDS slots of planes z-1, z, z+1.
+    auto collide = [&](int z, int sm, int s0, int sp, const T h[kQ]) {
+        if (!act) return;
+        // common velocity, first term of Eq. (SC_u_eq), in component order
+        T rho = 0, den = 0, num[3] = {0, 0, 0};
+        T rho_own = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const T rc = s_rho[s0][c][me];
+            T jc[3];
+            if (NC == 1) {
+                jc[0] = first_moment<T, 0>(h);
+                jc[1] = first_moment<T, 1>(h);
+                jc[2] = first_moment<T, 2>(h);
+            } else {
+                jc[0] = s_j[c][0][tl];
+                jc[1] = s_j[c][1][tl];
+                jc[2] = s_j[c][2][tl];
+            }
+            if (c == s) rho_own = rc;
+            rho += rc;
+            den += rc * a.inv_tau[c];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) num[d] += jc[d] * a.inv_tau[c];
+        }
+        const T inv_den = den > T(0) ? T(1) / den : T(0);
+        const T inv_rho = rho > T(0) ? T(1) / rho : T(0);
+        const int cn = CNS == 2 ? s : 0;
+        T ga[3];
+        stencil<T, float, LW>(s_ns[sm][cn], s_ns[s0][cn], s_ns[sp][cn], me, ga);
+        T gi[3] = {0, 0, 0};
+        if (NC == 2) stencil<T, T, LW>(s_rho[sm][1 - s], s_rho[s0][1 - s], s_rho[sp][1 - s], me, gi);
+        // force per unit density F_tot,s / rho_s (Eqs. SC_F_inter, SC_F_ads,
+        // SC_F_ext); no shift for an absent component
+        const bool present = rho_own > T(0);
+        const T tau_s = a.tau[s], inv_tau_s = a.inv_tau[s], Gads = a.Gads_s[s];
+        T ueq[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T acc = -a.G_s * gi[d] - Gads * ga[d] + a.F[d] * inv_rho;
+            ueq[d] = num[d] * inv_den + (present ? tau_s * acc : T(0));
+        }
+        const T uu = ueq[0] * ueq[0] + ueq[1] * ueq[1] + ueq[2] * ueq[2];
+        const T n = static_cast<T>(s_ns[s0][cn][me]);
+        const T omn = T(1) - n;
+        const T cb = omn * inv_tau_s;  // weight of h^eq
+        const T ca = omn - cb;         // weight of h
+        // cb*h^eq_i = K0 + K1 cu + K2 cu^2 per weight class
+        const T base0 = (rho_own - a.rho0[s]) - T(1.5) * rho_own * uu;
+        const T r3 = T(3) * rho_own, r45 = T(4.5) * rho_own;
+        T K0[3], K1[3], K2[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T wk = cb * (k == 0 ? T(1) / T(3) : (k == 1 ? T(1) / T(18) : T(1) / T(36)));
+            K0[k] = wk * base0;
+            K1[k] = wk * r3;
+            K2[k] = wk * r45;
+        }
+        const uint32_t zo = static_cast<uint32_t>(z) * plane_bytes;
+        ST::bst(ST::enc(ca * h[0] + n * h[0] + K0[0], a.scale), rb, own, zo);
+#pragma unroll
+        for (int i = 1; i <= 9; ++i) {
+            const int k = (CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]) == 1 ? 1 : 2;
+            T cu = T(0);
+            if (CX[i]) cu += CX[i] > 0 ? ueq[0] : -ueq[0];
+            if (CY[i]) cu += CY[i] > 0 ? ueq[1] : -ueq[1];
+            if (CZ[i]) cu += CZ[i] > 0 ? ueq[2] : -ueq[2];
+            const T t = K2[k] * (cu * cu) + K0[k];
+            const T e = K1[k] * cu;
+            const T post_i = ca * h[i] + (n * h[i + 9] + (t + e));
+            const T post_o = ca * h[i + 9] + (n * h[i] + (t - e));
+            ST::bst(ST::enc(post_i, a.scale), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
+            ST::bst(ST::enc(post_o, a.scale), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
+        }
+    };
+
+    T hA[kQ];
+    T hB[kQ];
+
+    // prologue: plane zs-1 (densities only, into slot 0), plane zs (kept in hA)
+    stage_plane(wrapz(zs - 1), 0, hB);
+    stage_plane(zs, 1, hA);
+
+    // sweep, two planes per iteration so the register sets alternate roles;
+    // slots (sm, s0, sp) hold planes (z-1, z, z+1)
+    int sm = 0, s0 = 1, sp = 2;
+    int z = zs;
+    for (; z + 1 < ze; z += 2) {
+        stage_plane(wrapz(z + 1), sp, hB);
+        publish_j(hA);
         __syncthreads();
+        collide(z, sm, s0, sp, hA);
+        __syncthreads();
+        stage_plane(wrapz(z + 2), sm, hA);  // slot of z-1 is free again
+        publish_j(hB);
+        __syncthreads();
+        collide(z + 1, s0, sp, sm, hB);
+        __syncthreads();
+        // planes z+1, z+2 now sit in slots sp, sm; s0 is free for z+3
+        const int t0 = sm;
+        sm = sp;
+        sp = s0;
+        s0 = t0;
+    }
+    if (z < ze) {
+        stage_plane(wrapz(z + 1), sp, hB);
+        publish_j(hA);
+        __syncthreads();
+        collide(z, sm, s0, sp, hA);
     }
 }
 
@@ -602,6 +730,11 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
 // ---------------------------------------------------------------------------
 // Launchers.
 
+bool tile_supported(int tx, int ty)
+{
+    return (tx == 64 && (ty == 4 || ty == 8)) || (tx == 32 && (ty == 4 || ty == 8 || ty == 16));
+}
+
 int storage_bytes(int storage)
 {
     switch (storage) {
@@ -613,7 +746,7 @@ int storage_bytes(int storage)
     }
 }
 
-template <typename ST, int NC, int CNS, int TY>
+template <typename ST, int NC, int CNS, int TX, int TY>
 static hipError_t step_t(const Problem& p, const Launch& l, const void* A, void* B, const float* ns,
                          hipStream_t st)
 {
@@ -621,21 +754,25 @@ static hipError_t step_t(const Problem& p, const Launch& l, const void* A, void*
     using E = typename ST::E;
     Args<T> a = make_args<T>(p);
     a.zchunk = l.zchunk;
-    a.ntx = (p.nx + kTileX - 1) / kTileX;
+    a.ntx = (p.nx + TX - 1) / TX;
     a.nty = (p.ny + TY - 1) / TY;
     a.nzc = (p.nz + l.zchunk - 1) / l.zchunk;
     const int nblocks = a.ntx * a.nty * a.nzc;
-    hipLaunchKernelGGL((k_step<ST, NC, CNS, TY>), dim3(nblocks), dim3(kTileX * TY), 0, st, a,
+    hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY>), dim3(nblocks), dim3(NC * TX * TY), 0, st, a,
                        static_cast<const E*>(A), static_cast<E*>(B), ns);
     return hipGetLastError();
 }
 
+// Tile shapes (TX x TY cells per block) compiled in.
 template <typename ST, int NC, int CNS>
 static hipError_t step_ty(const Problem& p, const Launch& l, const void* A, void* B, const float* ns,
                           hipStream_t st)
 {
-    if (l.tile_y == 4) return step_t<ST, NC, CNS, 4>(p, l, A, B, ns, st);
-    if (l.tile_y == 8) return step_t<ST, NC, CNS, 8>(p, l, A, B, ns, st);
+    if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4>(p, l, A, B, ns, st);
+    if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8>(p, l, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4>(p, l, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8>(p, l, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16>(p, l, A, B, ns, st);
     return hipErrorInvalidValue;
 }
 

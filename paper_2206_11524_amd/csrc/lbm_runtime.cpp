@@ -55,6 +55,9 @@ int validate(const lbm_domain* d, const lbm_params* p)
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->F_ext[a])) return LBM_EINVAL;
     if (p->storage < LBM_F64 || p->storage > LBM_BF16S) return LBM_EINVAL;
+    // the step kernel addresses the 19 direction arrays of one component through
+    // one 32-bit buffer range
+    if (static_cast<uint64_t>(N) * hm::kQ * hm::storage_bytes(p->storage) >= (uint64_t(1) << 32)) return LBM_EINVAL;
     if (p->store_scale_log2 < -30 || p->store_scale_log2 > 30) return LBM_EINVAL;
     if ((p->storage == LBM_F64 || p->storage == LBM_F32) && p->store_scale_log2 != 0) return LBM_EINVAL;
     if (p->n_res < 0 || p->n_res > LBM_MAX_RES) return LBM_EINVAL;
@@ -112,16 +115,20 @@ hm::Launch choose_launch(const hm::Problem& p)
     // FP64 with two components needs the smaller tile to stay within the
     // register file (no spills)
     const bool wide = p.storage == hm::kF64 && p.ncomp == 2;
+    l.tile_x = env_int("LBM_TILE_X", 64);
     l.tile_y = env_int("LBM_TILE_Y", (p.ny >= 8 && !wide) ? 8 : 4);
-    if (l.tile_y != 4 && l.tile_y != 8) l.tile_y = 8;
-    const int ntx = (p.nx + hm::kTileX - 1) / hm::kTileX;
+    if (!hm::tile_supported(l.tile_x, l.tile_y)) {
+        l.tile_x = 64;
+        l.tile_y = wide ? 4 : 8;
+    }
+    const int ntx = (p.nx + l.tile_x - 1) / l.tile_x;
     const int nty = (p.ny + l.tile_y - 1) / l.tile_y;
     const int64_t cols = static_cast<int64_t>(ntx) * nty;
     int zc = env_int("LBM_ZCHUNK", 0);
     if (zc <= 0) {
-        // aim at >= 1024 blocks, but keep the z-halo (2 planes per chunk) small
-        const int64_t want_chunks = std::max<int64_t>(1, (1024 + cols - 1) / cols);
-        zc = static_cast<int>(std::max<int64_t>(16, (p.nz + want_chunks - 1) / want_chunks));
+        // aim at >= 512 blocks, but keep the z-halo (2 planes per chunk) small
+        const int64_t want_chunks = std::max<int64_t>(1, (512 + cols - 1) / cols);
+        zc = static_cast<int>(std::max<int64_t>(32, (p.nz + want_chunks - 1) / want_chunks));
     }
     l.zchunk = std::min(std::max(zc, 1), p.nz);
     return l;

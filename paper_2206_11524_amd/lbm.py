@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libhmcsc.so")
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(PKG, "libhmcsc.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ENOTFOUND, LBM_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
@@ -101,14 +101,13 @@ def _check(code: int, what: str):
 
 def default_shift(storage: str, ncomp: int, rho_init: np.ndarray):
     """Shift rho0 for the stored populations: zero for the plain FP64/FP32
-    formats, the midpoint of each component's initial density range for the
-    16-bit formats."""
+    formats; for the 16-bit formats the smallest initial density of each
+    component (its dissolved density in a two-phase set-up), so populations of
+    a component where it is dilute are stored as small numbers with full
+    relative precision."""
     if storage in ("f64", "f32"):
         return (0.0, 0.0)
-    out = []
-    for s in range(ncomp):
-        r = rho_init[s]
-        out.append(float(0.5 * (r.min() + r.max())))
+    out = [float(rho_init[s].min()) for s in range(ncomp)]
     return tuple(out + [0.0] * (2 - len(out)))
 
 
