@@ -97,6 +97,28 @@ def run_variant(w, storage, steps, warmup):
     }
 
 
+def stream_copy_gbs(mib=2048, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time) on this GPU,
+    the practical streaming ceiling the step kernel is compared with."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The FP64 CPU oracle on the same workload, timed on the host cores for a
     bounded number of whole-domain steps."""
@@ -190,6 +212,9 @@ def main():
     }
     if "f32" in results and "f16s" in results:
         line["fp16_gain_over_fp32"] = round(results["f16s"]["mlups"] / results["f32"]["mlups"], 3)
+    copy = stream_copy_gbs()
+    line["stream_copy_GBs"] = round(copy, 1)
+    line["roofline"]["frac_of_stream_copy"] = round(head["roofline"]["achieved"] / copy, 4)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)
