@@ -176,6 +176,107 @@ void lbm_destroy(lbm_ctx* ctx);
 /* Static text for an LBM_E* code. */
 const char* lbm_strerror(int code);
 
+/* ---------------------------------------------------------------------------
+ * Batched stepping: many domains, one kernel launch per step.
+ *
+ * A group steps a fixed set of contexts together; each launch runs the update
+ * of every domain (same storage format, component count and n_s count) over a
+ * device table of domains, so small domains share the GPU instead of each
+ * paying a launch.  Results are bitwise those of lbm_step on each context.
+ */
+typedef struct lbm_group lbm_group;
+
+/* Group the n contexts ctxs[0..n-1] (caller keeps ownership; they must
+ * outlive the group and not be stepped on their own meanwhile).  Work is
+ * queued on the stream of ctxs[0].  LBM_EINVAL if they differ in storage,
+ * ncomp or c_ns, or n < 1. */
+int lbm_group_create(lbm_ctx* const* ctxs, int32_t n, lbm_group** out);
+
+/* Advance every context of the group by nsteps (asynchronous; launches are
+ * replayed from a captured HIP graph).  Each context's time advances. */
+int lbm_group_step(lbm_group* g, int64_t nsteps);
+
+/* Average device time in ms of one batched launch of the last lbm_group_step. */
+double lbm_group_last_step_ms(const lbm_group* g);
+
+void lbm_group_destroy(lbm_group* g);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of simulation requests.
+ *
+ * A server owns a worker thread and a stream.  Requests (domain, n_s, initial
+ * densities, parameters, step budget, convergence tolerance) are queued by
+ * lbm_batch_submit from any thread.  Each tick the worker admits queued
+ * requests while a slot is free and the resident state fits the HBM budget,
+ * replays a captured graph of steps_per_tick batched launches over all
+ * resident domains (a domain that needs fewer steps stops early), checks the
+ * FP64 momentum of each domain, and retires those that reached their step
+ * budget or converged.  Each result is the same as running the request alone.
+ */
+typedef struct lbm_server lbm_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* resident population + n_s bytes; 0: 90 % of free device memory */
+    int32_t max_slots;         /* domains resident at once (>= 1)                            */
+    int32_t steps_per_tick;    /* launches per graph replay and between checks (>= 1)         */
+    int32_t storage;           /* lbm_storage of every request                               */
+    int32_t ncomp, c_ns;       /* component and n_s-field counts of every request            */
+    int64_t max_cells;         /* largest accepted domain (sizes the shared scratch)         */
+    int32_t tile_x, tile_y;    /* tile of the batched kernel; 0: 64 x 8                      */
+} lbm_server_cfg;
+
+typedef struct {
+    lbm_domain dom;
+    const float* n_s;         /* [c_ns][N], copied at submit                                 */
+    const double* rho_init;   /* [ncomp][N], copied at submit                                */
+    lbm_params params;        /* storage, ncomp and c_ns must match the server               */
+    int64_t max_steps;        /* run at most this many steps (>= 1)                          */
+    double conv_tol;          /* stop when |J(t) - J(t-K)| <= conv_tol |J(t)|, K = steps_per_tick;
+                                 0 disables                                                  */
+    double* rho_out;          /* optional caller buffer [ncomp][N] for the final densities;
+                                 must stay valid until the result is final                   */
+} lbm_request;
+
+typedef struct {
+    int32_t status;       /* LBM_OK or the error that ended the request   */
+    int32_t converged;    /* 1 if stopped by the convergence test          */
+    int64_t steps_done;
+    double t_submit;      /* seconds on the server clock                    */
+    double t_admit;
+    double t_done;
+    lbm_totals totals;    /* FP64 totals of the final state                 */
+} lbm_result;
+
+typedef struct {
+    int64_t submitted, completed, queued, active;
+    double cell_updates;   /* cell updates executed (all domains)        */
+    double busy_seconds;   /* time with at least one resident domain      */
+    double uptime_seconds;
+    uint64_t bytes_resident;
+    int64_t ticks;
+} lbm_server_stats;
+
+/* Create a server on the current device.  reserved must be NULL. */
+int lbm_server_create(const lbm_server_cfg* cfg, void* reserved, lbm_server** out);
+
+/* Queue a request; *ticket identifies it.  LBM_EINVAL for invalid input or a
+ * format mismatch, LBM_ENOMEM if its state can never fit the budget or it
+ * exceeds max_cells. Thread-safe. */
+int lbm_batch_submit(lbm_server* s, const lbm_request* req, uint64_t* ticket);
+
+/* Result of a ticket: LBM_OK and *out filled when final, LBM_EAGAIN while
+ * queued or running, LBM_ENOTFOUND for an unknown ticket.  Thread-safe. */
+int lbm_batch_poll(lbm_server* s, uint64_t ticket, lbm_result* out);
+
+/* Like lbm_batch_poll but blocks up to timeout_s seconds (< 0: forever). */
+int lbm_batch_wait(lbm_server* s, uint64_t ticket, double timeout_s, lbm_result* out);
+
+int lbm_server_stats_get(lbm_server* s, lbm_server_stats* out);
+
+/* Stop the worker (queued and running requests end with LBM_EAGAIN status),
+ * free all device memory.  NULL is ignored. */
+void lbm_server_destroy(lbm_server* s);
+
 #ifdef __cplusplus
 }
 #endif

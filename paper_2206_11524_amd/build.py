@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhmcsc.so")
-SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp", "lbm_batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -44,7 +44,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed: " + " ".join(cmd))
     tmp = LIB + ".tmp"
-    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

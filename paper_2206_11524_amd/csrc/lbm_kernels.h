@@ -74,4 +74,29 @@ hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipSt
 
 int moments_max_blocks();
 
+// One domain of a batched launch (host description).
+struct BatchDomain {
+    Problem prob;
+    int zchunk;
+    const void* buf[2];  // population buffers (ping-pong)
+    const float* ns;
+    int parity;          // buffer holding the state before the first launch of the tick
+    int steps;           // launches k = 0 .. steps-1 of the tick advance this domain
+};
+
+// Size of a device table for up to max_domains domains.
+size_t batch_table_bytes(int storage, int max_domains);
+
+// Encode the table for n domains into host memory (batch_table_bytes bytes);
+// returns the total number of tiles.  Upload it to the device before launching.
+int batch_encode(int storage, const BatchDomain* d, int n, int tile_x, int tile_y, void* host);
+
+// Tile shapes compiled for the batched kernel.
+bool batch_tile_supported(int tile_x, int tile_y);
+
+// Launch k of a tick: every domain with k < steps takes one step.  The grid
+// strides over all tiles of the table, so any fixed grid size works.
+hipError_t launch_step_batch(int storage, int ncomp, int c_ns, int tile_x, int tile_y, const void* table, int k,
+                             int grid, hipStream_t st);
+
 }  // namespace hm

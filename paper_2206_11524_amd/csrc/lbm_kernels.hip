@@ -294,10 +294,22 @@ __device__ __forceinline__ void stencil(const V* pm, const V* p0, const V* pp, i
 // components of a cell meet only through LDS (densities and first moments),
 // which halves the registers per thread and doubles the waves per CU.
 template <typename ST, int NC, int CNS, int TX, int TY>
-__global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
-                                                          const typename ST::E* __restrict__ A,
-                                                          typename ST::E* __restrict__ B,
-                                                          const float* __restrict__ ns)
+struct TileShared {
+    using T = typename ST::T;
+    static constexpr int LW = TX + 2;
+    static constexpr int LP = LW * (TY + 2);
+    static constexpr int NTC = TX * TY;
+    T rho[3][NC][LP];
+    float ns[3][CNS][LP];
+    T j[NC][3][NTC];
+};
+
+// The sweep of one tile column (logical tile index L of the domain described
+// by a).  Shared by the single-domain and the batched kernels.
+template <typename ST, int NC, int CNS, int TX, int TY>
+__device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const typename ST::E* __restrict__ A,
+                                          typename ST::E* __restrict__ B, const float* __restrict__ ns, int L,
+                                          TileShared<ST, NC, CNS, TX, TY>& sh)
 {
     using T = typename ST::T;
     using E = typename ST::E;
@@ -306,16 +318,10 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
     constexpr int NTC = TX * TY;  // threads per component
     constexpr int NT = NC * NTC;
     constexpr int NSMAX = (LP + NT - 1) / NT;  // n_s cells staged per thread and plane
+    auto& s_rho = sh.rho;
+    auto& s_ns = sh.ns;
+    auto& s_j = sh.j;
 
-    __shared__ T s_rho[3][NC][LP];
-    __shared__ float s_ns[3][CNS][LP];
-    __shared__ T s_j[NC][3][NTC];
-
-    // XCD-aware tile order: blocks are dispatched round-robin over 8 XCDs, so
-    // give each XCD a contiguous run of tiles (neighbours share its L2).
-    const int nb = gridDim.x;
-    int L = blockIdx.x;
-    if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
     const int tx = L % a.ntx;
     const int ty = (L / a.ntx) % a.nty;
     const int tz = L / (a.ntx * a.nty);
@@ -532,6 +538,74 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
         publish_j(hA);
         __syncthreads();
         collide(z, sm, s0, sp, hA);
+    }
+}
+
+template <typename ST, int NC, int CNS, int TX, int TY>
+__global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
+                                                      const typename ST::E* __restrict__ A,
+                                                      typename ST::E* __restrict__ B,
+                                                      const float* __restrict__ ns)
+{
+    __shared__ TileShared<ST, NC, CNS, TX, TY> sh;
+    // XCD-aware tile order: blocks are dispatched round-robin over 8 XCDs, so
+    // give each XCD a contiguous run of tiles (neighbours share its L2).
+    const int nb = gridDim.x;
+    int L = blockIdx.x;
+    if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+    step_tile<ST, NC, CNS, TX, TY>(a, A, B, ns, L, sh);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched step: the tiles of many domains in one launch.  The device table
+// holds a header and one entry per domain (geometry, parameters, ping-pong
+// buffers, steps to take in this tick, first tile index).  Blocks stride over
+// the concatenated tile list, so the grid size does not depend on the mix and
+// a captured graph of K launches (k = 0..K-1) stays valid when domains come
+// and go: only the table changes.
+template <typename T>
+struct BatchEntry {
+    Args<T> a;
+    const void* buf[2];
+    const float* ns;
+    int parity;      // buffer holding the state at k = 0
+    int steps;       // launches k < steps advance this domain
+    int tile_begin;  // first tile of this domain in the concatenated list
+    int ntiles;
+};
+
+struct BatchHeader {
+    int ndom;
+    int total_tiles;
+    int pad[2];
+};
+
+constexpr size_t kBatchEntryOffset = 64;
+
+template <typename ST, int NC, int CNS, int TX, int TY>
+__global__ __launch_bounds__(NC* TX* TY) void k_step_batch(const char* __restrict__ table, int k)
+{
+    using T = typename ST::T;
+    using E = typename ST::E;
+    __shared__ TileShared<ST, NC, CNS, TX, TY> sh;
+    const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(table);
+    const BatchEntry<T>* ent = reinterpret_cast<const BatchEntry<T>*>(table + kBatchEntryOffset);
+    const int total = hdr->total_tiles;
+    const int nd = hdr->ndom;
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        int lo = 0, hi = nd - 1;  // last domain with tile_begin <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ent[mid].tile_begin <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchEntry<T>& e = ent[lo];
+        if (k >= e.steps) continue;
+        const int cur = (e.parity + k) & 1;
+        __syncthreads();  // the previous tile's LDS is no longer read
+        step_tile<ST, NC, CNS, TX, TY>(e.a, static_cast<const E*>(e.buf[cur]), static_cast<E*>(const_cast<void*>(e.buf[1 - cur])),
+                                       e.ns, w - e.tile_begin, sh);
     }
 }
 
@@ -876,6 +950,92 @@ hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipSt
 {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, st, partials, nblocks, out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches.
+
+template <typename T>
+static size_t batch_bytes_t(int max_domains)
+{
+    return kBatchEntryOffset + sizeof(BatchEntry<T>) * static_cast<size_t>(max_domains > 0 ? max_domains : 1);
+}
+
+size_t batch_table_bytes(int storage, int max_domains)
+{
+    return storage == kF64 ? batch_bytes_t<double>(max_domains) : batch_bytes_t<float>(max_domains);
+}
+
+template <typename T>
+static int batch_encode_t(const BatchDomain* d, int n, int tile_x, int tile_y, void* host)
+{
+    BatchHeader* h = static_cast<BatchHeader*>(host);
+    BatchEntry<T>* e = reinterpret_cast<BatchEntry<T>*>(static_cast<char*>(host) + kBatchEntryOffset);
+    int tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        Args<T> a = make_args<T>(d[i].prob);
+        a.zchunk = d[i].zchunk;
+        a.ntx = (d[i].prob.nx + tile_x - 1) / tile_x;
+        a.nty = (d[i].prob.ny + tile_y - 1) / tile_y;
+        a.nzc = (d[i].prob.nz + a.zchunk - 1) / a.zchunk;
+        e[i].a = a;
+        e[i].buf[0] = d[i].buf[0];
+        e[i].buf[1] = d[i].buf[1];
+        e[i].ns = d[i].ns;
+        e[i].parity = d[i].parity;
+        e[i].steps = d[i].steps;
+        e[i].tile_begin = tiles;
+        e[i].ntiles = a.ntx * a.nty * a.nzc;
+        tiles += e[i].ntiles;
+    }
+    h->ndom = n;
+    h->total_tiles = tiles;
+    h->pad[0] = h->pad[1] = 0;
+    return tiles;
+}
+
+int batch_encode(int storage, const BatchDomain* d, int n, int tile_x, int tile_y, void* host)
+{
+    return storage == kF64 ? batch_encode_t<double>(d, n, tile_x, tile_y, host)
+                           : batch_encode_t<float>(d, n, tile_x, tile_y, host);
+}
+
+template <typename ST, int NC, int CNS, int TX, int TY>
+static hipError_t batch_t(const void* table, int k, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_step_batch<ST, NC, CNS, TX, TY>), dim3(grid), dim3(NC * TX * TY), 0, st,
+                       static_cast<const char*>(table), k);
+    return hipGetLastError();
+}
+
+template <typename ST, int NC, int CNS>
+static hipError_t batch_tile(int tx, int ty, const void* table, int k, int grid, hipStream_t st)
+{
+    if (tx == 64 && ty == 8) return batch_t<ST, NC, CNS, 64, 8>(table, k, grid, st);
+    if (tx == 32 && ty == 8) return batch_t<ST, NC, CNS, 32, 8>(table, k, grid, st);
+    return hipErrorInvalidValue;
+}
+
+template <typename ST>
+static hipError_t batch_st(int ncomp, int c_ns, int tx, int ty, const void* table, int k, int grid, hipStream_t st)
+{
+    if (ncomp == 1) return batch_tile<ST, 1, 1>(tx, ty, table, k, grid, st);
+    if (c_ns == 1) return batch_tile<ST, 2, 1>(tx, ty, table, k, grid, st);
+    return batch_tile<ST, 2, 2>(tx, ty, table, k, grid, st);
+}
+
+bool batch_tile_supported(int tx, int ty) { return (tx == 64 && ty == 8) || (tx == 32 && ty == 8); }
+
+hipError_t launch_step_batch(int storage, int ncomp, int c_ns, int tile_x, int tile_y, const void* table, int k,
+                             int grid, hipStream_t st)
+{
+    switch (storage) {
+    case kF64: return batch_st<F64>(ncomp, c_ns, tile_x, tile_y, table, k, grid, st);
+    case kF32: return batch_st<F32>(ncomp, c_ns, tile_x, tile_y, table, k, grid, st);
+    case kF16: return batch_st<F16>(ncomp, c_ns, tile_x, tile_y, table, k, grid, st);
+    case kBF16: return batch_st<BF16>(ncomp, c_ns, tile_x, tile_y, table, k, grid, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace hm

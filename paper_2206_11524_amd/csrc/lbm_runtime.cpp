@@ -13,31 +13,9 @@
 #include <new>
 #include <vector>
 
-#include "lbm_kernels.h"
+#include "lbm_internal.h"
 
-namespace {
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Scratch layout: [rho ncomp*N][u 3N][p N][partials][totals 5] (FP64).
-struct ScratchLayout {
-    size_t rho, u, p, partials, totals, bytes;
-};
-
-ScratchLayout scratch_layout(int64_t N, int ncomp)
-{
-    ScratchLayout s{};
-    size_t off = 0;
-    s.rho = off; off = align_up(off + sizeof(double) * static_cast<size_t>(ncomp) * N);
-    s.u = off; off = align_up(off + sizeof(double) * 3 * static_cast<size_t>(N));
-    s.p = off; off = align_up(off + sizeof(double) * static_cast<size_t>(N));
-    s.partials = off; off = align_up(off + sizeof(double) * 5 * hm::moments_max_blocks());
-    s.totals = off; off = align_up(off + sizeof(double) * 5);
-    s.bytes = off;
-    return s;
-}
+namespace hm_rt {
 
 int validate(const lbm_domain* d, const lbm_params* p)
 {
@@ -134,31 +112,42 @@ hm::Launch choose_launch(const hm::Problem& p)
     return l;
 }
 
-}  // namespace
+}  // namespace hm_rt
 
-struct lbm_ctx {
-    lbm_domain dom;
-    lbm_params prm;
-    hm::Problem prob;
-    hm::Launch launch;
-    lbm_sizes sizes;
-    ScratchLayout sl;
-    void* buf[2];
-    float* ns;
-    char* scratch;
-    bool owned;
-    hipStream_t stream;
-    int device;
-    int cur;  // index of the buffer holding the current state
-    int64_t t;
-    hipEvent_t ev0, ev1;
-    int64_t timed_steps;
-};
+using namespace hm_rt;
 
 #define HIP_TRY(expr)                                  \
     do {                                               \
         if ((expr) != hipSuccess) return LBM_EDEVICE;  \
     } while (0)
+
+int hm_rt::compute_totals(lbm_ctx* c, bool fields, lbm_totals* tot)
+{
+    double* rho = reinterpret_cast<double*>(c->scratch + c->sl.rho);
+    double* u = reinterpret_cast<double*>(c->scratch + c->sl.u);
+    double* p = reinterpret_cast<double*>(c->scratch + c->sl.p);
+    double* part = reinterpret_cast<double*>(c->scratch + c->sl.partials);
+    double* tots = reinterpret_cast<double*>(c->scratch + c->sl.totals);
+    int nb = 0;
+    HIP_TRY(hm::launch_density(c->prob, c->buf[c->cur], rho, c->stream));
+    HIP_TRY(hm::launch_moments(c->prob, c->buf[c->cur], c->ns, rho, fields ? u : nullptr, fields ? p : nullptr,
+                               part, &nb, c->stream));
+    HIP_TRY(hm::launch_reduce(part, nb, tots, c->stream));
+    double h[5];
+    HIP_TRY(hipMemcpyAsync(h, tots, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (tot) {
+        tot->mass[0] = h[0];
+        tot->mass[1] = c->prm.ncomp == 2 ? h[1] : 0.0;
+        for (int a = 0; a < 3; ++a) tot->momentum[a] = h[2 + a];
+        tot->time = c->t;
+        int fin = 1;
+        for (double v : h) fin &= std::isfinite(v) ? 1 : 0;
+        tot->finite = fin;
+        tot->pad = 0;
+    }
+    return LBM_OK;
+}
 
 extern "C" {
 
@@ -274,34 +263,6 @@ int lbm_create(const lbm_domain* dom, const float* n_s, const double* rho_init, 
         return LBM_EDEVICE;
     }
     *out = c;
-    return LBM_OK;
-}
-
-static int compute_totals(lbm_ctx* c, bool fields, lbm_totals* tot)
-{
-    double* rho = reinterpret_cast<double*>(c->scratch + c->sl.rho);
-    double* u = reinterpret_cast<double*>(c->scratch + c->sl.u);
-    double* p = reinterpret_cast<double*>(c->scratch + c->sl.p);
-    double* part = reinterpret_cast<double*>(c->scratch + c->sl.partials);
-    double* tots = reinterpret_cast<double*>(c->scratch + c->sl.totals);
-    int nb = 0;
-    HIP_TRY(hm::launch_density(c->prob, c->buf[c->cur], rho, c->stream));
-    HIP_TRY(hm::launch_moments(c->prob, c->buf[c->cur], c->ns, rho, fields ? u : nullptr, fields ? p : nullptr,
-                               part, &nb, c->stream));
-    HIP_TRY(hm::launch_reduce(part, nb, tots, c->stream));
-    double h[5];
-    HIP_TRY(hipMemcpyAsync(h, tots, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (tot) {
-        tot->mass[0] = h[0];
-        tot->mass[1] = c->prm.ncomp == 2 ? h[1] : 0.0;
-        for (int a = 0; a < 3; ++a) tot->momentum[a] = h[2 + a];
-        tot->time = c->t;
-        int fin = 1;
-        for (double v : h) fin &= std::isfinite(v) ? 1 : 0;
-        tot->finite = fin;
-        tot->pad = 0;
-    }
     return LBM_OK;
 }
 

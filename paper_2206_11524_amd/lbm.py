@@ -258,3 +258,156 @@ def from_workload(w, storage="f32", rho_shift=None, store_scale_log2=0, check_ev
                     g_scale=w.g_scale, storage=storage, rho_shift=rho_shift,
                     store_scale_log2=store_scale_log2, reservoirs=w.reservoirs, check_every=check_every)
     return Simulation(w.shape, w.ns, w.rho, p, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Batched stepping and serving.
+
+class ServerCfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int32), ("steps_per_tick", C.c_int32),
+                ("storage", C.c_int32), ("ncomp", C.c_int32), ("c_ns", C.c_int32), ("max_cells", C.c_int64),
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("dom", Domain), ("n_s", C.c_void_p), ("rho_init", C.c_void_p), ("params", Params),
+                ("max_steps", C.c_int64), ("conv_tol", C.c_double), ("rho_out", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("converged", C.c_int32), ("steps_done", C.c_int64),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double), ("totals", Totals)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("queued", C.c_int64), ("active", C.c_int64),
+                ("cell_updates", C.c_double), ("busy_seconds", C.c_double), ("uptime_seconds", C.c_double),
+                ("bytes_resident", C.c_uint64), ("ticks", C.c_int64)]
+
+
+SERVE_SIGNATURES = {
+    "lbm_group_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "lbm_group_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_group_last_step_ms": (C.c_double, [C.c_void_p]),
+    "lbm_group_destroy": (None, [C.c_void_p]),
+    "lbm_server_create": (C.c_int, [C.POINTER(ServerCfg), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_batch_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "lbm_batch_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Result)]),
+    "lbm_batch_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double, C.POINTER(Result)]),
+    "lbm_server_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "lbm_server_destroy": (None, [C.c_void_p]),
+}
+
+
+def _serve_lib():
+    lib = _lib()
+    if not getattr(lib, "_serve_ready", False):
+        for name, (res, args) in SERVE_SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        lib._serve_ready = True
+    return lib
+
+
+class Group:
+    """Several Simulations stepped together, one batched launch per step."""
+
+    def __init__(self, sims):
+        self.lib = _serve_lib()
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s.ctx.value for s in self.sims])
+        g = C.c_void_p()
+        _check(self.lib.lbm_group_create(arr, len(self.sims), C.byref(g)), "lbm_group_create")
+        self.g = g
+
+    def step(self, n: int):
+        _check(self.lib.lbm_group_step(self.g, int(n)), "lbm_group_step")
+
+    def last_step_ms(self) -> float:
+        return float(self.lib.lbm_group_last_step_ms(self.g))
+
+    def close(self):
+        if getattr(self, "g", None):
+            self.lib.lbm_group_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server (worker thread inside the library)."""
+
+    def __init__(self, storage="f16s", ncomp=2, c_ns=1, max_slots=64, steps_per_tick=100, max_cells=192 ** 3,
+                 hbm_budget_bytes=0, tile=(64, 8)):
+        self.lib = _serve_lib()
+        cfg = ServerCfg(int(hbm_budget_bytes), int(max_slots), int(steps_per_tick),
+                        STORAGE[storage] if isinstance(storage, str) else int(storage), ncomp, c_ns,
+                        int(max_cells), tile[0], tile[1])
+        s = C.c_void_p()
+        _check(self.lib.lbm_server_create(C.byref(cfg), None, C.byref(s)), "lbm_server_create")
+        self.s = s
+        self.storage = storage
+        self._keep = {}
+
+    def submit(self, shape, ns, rho_init, params: Params, max_steps: int, conv_tol: float = 0.0,
+               want_rho: bool = False) -> int:
+        ns = np.ascontiguousarray(ns, dtype=np.float32)
+        rho_init = np.ascontiguousarray(rho_init, dtype=np.float64)
+        out = np.empty_like(rho_init) if want_rho else None
+        rq = Request(Domain(*[int(v) for v in shape]), ns.ctypes.data, rho_init.ctypes.data, params,
+                     int(max_steps), float(conv_tol), out.ctypes.data if out is not None else None)
+        t = C.c_uint64()
+        _check(self.lib.lbm_batch_submit(self.s, C.byref(rq), C.byref(t)), "lbm_batch_submit")
+        if out is not None:
+            self._keep[t.value] = out
+        return t.value
+
+    def submit_workload(self, w, max_steps, conv_tol=0.0, want_rho=False, rho_shift=None):
+        if rho_shift is None:
+            rho_shift = default_shift(self.storage, w.ncomp, w.rho)
+        p = make_params(ncomp=w.ncomp, c_ns=w.c_ns, tau=w.tau, G=w.G, G_ads=w.G_ads, F_ext=w.F_ext,
+                        g_scale=w.g_scale, storage=self.storage, rho_shift=rho_shift, reservoirs=w.reservoirs)
+        return self.submit(w.shape, w.ns, w.rho, p, max_steps, conv_tol, want_rho)
+
+    def poll(self, ticket):
+        r = Result()
+        rc = self.lib.lbm_batch_poll(self.s, C.c_uint64(ticket), C.byref(r))
+        if rc == LBM_EAGAIN:
+            return None
+        _check(rc, "lbm_batch_poll")
+        return self._result(ticket, r)
+
+    def wait(self, ticket, timeout_s=-1.0):
+        r = Result()
+        rc = self.lib.lbm_batch_wait(self.s, C.c_uint64(ticket), float(timeout_s), C.byref(r))
+        if rc == LBM_EAGAIN:
+            return None
+        _check(rc, "lbm_batch_wait")
+        return self._result(ticket, r)
+
+    def _result(self, ticket, r):
+        return {"status": r.status, "converged": bool(r.converged), "steps_done": r.steps_done,
+                "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done,
+                "mass": list(r.totals.mass), "momentum": list(r.totals.momentum),
+                "rho": self._keep.pop(ticket, None)}
+
+    def stats(self):
+        st = ServerStats()
+        _check(self.lib.lbm_server_stats_get(self.s, C.byref(st)), "lbm_server_stats_get")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "s", None):
+            self.lib.lbm_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

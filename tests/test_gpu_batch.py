@@ -1,0 +1,168 @@
+"""Batched stepping and continuous-batching serving on the GPU.
+
+* A group of domains (different shapes, parameters, ragged tiles) stepped by
+  one batched launch per step gives bit-for-bit the populations of each domain
+  stepped alone by lbm_step, with and without graph replay, and the FP64 path
+  matches the oracle.
+* The server: every request's result (final densities, FP64 totals) is bit for
+  bit the result of running that request alone for the same number of steps,
+  whatever else shared the GPU; admission respects the HBM budget; errors are
+  reported per request.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2206_11524_amd import inputs, lbm
+
+from _common import oracle_for, rel_max_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+def _domains(storage):
+    ws = []
+    w = inputs.droplet(n=24, radius=6, seed=3)
+    ws.append(w)
+    w = inputs.random_state((70, 13, 11), 201, c_ns=1, ns_choices=[0.0, 0.3, 1.0], rho_range=(0.3, 0.7))
+    w.G, w.G_ads, w.F_ext, w.tau = 0.7, (0.2, -0.1), (1e-4, 0, 2e-4), (0.8, 1.2)
+    w.reservoirs = [(2, 0, 1, (0.6, 0.4))]
+    ws.append(w)
+    ws.append(inputs.porous_domain(32, 3001))
+    w = inputs.random_state((5, 40, 9), 202, c_ns=1, ns_choices=[0.0, 0.5], rho_range=(0.4, 0.6))
+    w.G = 0.5
+    ws.append(w)
+    return ws
+
+
+def _alone(w, storage, steps):
+    sim = lbm.from_workload(w, storage=storage)
+    sim.step(steps)
+    f = sim.populations()
+    sim.close()
+    return f
+
+
+@pytest.mark.parametrize("storage,own_stream", [("f32", False), ("f32", True), ("f16s", True), ("f64", False)])
+def test_group_is_bitwise_each_domain_alone(storage, own_stream):
+    import torch
+    ws = _domains(storage)
+    steps = 37  # 16 + 16 + 5: graph replays and direct launches
+    ref = [_alone(w, storage, steps) for w in ws]
+    stream = torch.cuda.Stream() if own_stream else None
+    ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream())
+    with ctx:
+        sims = [lbm.from_workload(w, storage=storage) for w in ws]
+        g = lbm.Group(sims)
+        g.step(steps)
+        got = [s.populations() for s in sims]
+        assert all(s.time == steps for s in sims)
+        g.close()
+        for s in sims:
+            s.close()
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+
+
+def test_group_fp64_matches_oracle():
+    ws = _domains("f64")
+    sims = [lbm.from_workload(w, storage="f64") for w in ws]
+    g = lbm.Group(sims)
+    g.step(20)
+    for w, s in zip(ws, sims):
+        o = oracle_for(w)
+        fo = o.run(o.init(w.rho), 20)
+        assert rel_max_err(s.populations(), fo) < 1e-10
+    g.close()
+    for s in sims:
+        s.close()
+
+
+def test_server_results_equal_running_alone():
+    storage = "f16s"
+    srv = lbm.Server(storage=storage, max_slots=4, steps_per_tick=25, max_cells=48 ** 3)
+    ws = [inputs.porous_domain(e, 4000 + k) for k, e in enumerate([24, 32, 48, 32, 40, 24, 48])]
+    steps = [60, 25, 110, 7, 75, 140, 50]
+    tickets = [srv.submit_workload(w, s, want_rho=True) for w, s in zip(ws, steps)]
+    # one request with a convergence stop
+    wc = inputs.porous_domain(32, 4100)
+    wc.G, wc.G_ads, wc.F_ext = 0.0, (0.0, 0.0), (0.0, 0.0, 1e-5)
+    tc = srv.submit_workload(wc, 100000, conv_tol=1e-3, want_rho=True)
+    res = [srv.wait(t, 120.0) for t in tickets]
+    rc = srv.wait(tc, 120.0)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(ws) + 1 and st["ticks"] > 0
+    for w, n, r in zip(ws, steps, res):
+        assert r is not None and r["status"] == 0 and r["steps_done"] == n
+        sim = lbm.from_workload(w, storage=storage)
+        sim.step(n)
+        m = sim.moments()
+        sim.close()
+        assert np.array_equal(r["rho"], m["rho"])
+        assert r["mass"][:2] == list(m["mass"])
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+    assert rc["status"] == 0 and rc["converged"] and rc["steps_done"] % 25 == 0
+    sim = lbm.from_workload(wc, storage=storage)
+    sim.step(rc["steps_done"])
+    m = sim.moments()
+    sim.close()
+    assert np.array_equal(rc["rho"], m["rho"])
+
+
+def test_server_admission_respects_budget():
+    storage = "f32"
+    w = inputs.porous_domain(40, 5000)
+    one = 2 * lbm.required_bytes(w.shape, lbm.make_params(storage=storage)).pop_bytes + 4 * w.ncells
+    srv = lbm.Server(storage=storage, max_slots=8, steps_per_tick=50, max_cells=40 ** 3,
+                     hbm_budget_bytes=int(1.5 * one))
+    t1 = srv.submit_workload(w, 300)
+    t2 = srv.submit_workload(inputs.porous_domain(40, 5001), 300)
+    r1, r2 = srv.wait(t1, 120.0), srv.wait(t2, 120.0)
+    srv.close()
+    assert r1["status"] == 0 and r2["status"] == 0
+    # the second could only be admitted once the first had left
+    assert r2["t_admit"] >= r1["t_done"] - 1e-6
+
+
+def test_server_rejects_and_reports():
+    srv = lbm.Server(storage="f16s", max_slots=2, steps_per_tick=10, max_cells=32 ** 3,
+                     hbm_budget_bytes=10 ** 6)
+    w = inputs.porous_domain(40, 5002)
+    with pytest.raises(lbm.LbmError) as e:   # larger than max_cells
+        srv.submit_workload(w, 10)
+    assert e.value.code == lbm.LBM_ENOMEM
+    w = inputs.porous_domain(32, 5003)
+    with pytest.raises(lbm.LbmError) as e:   # never fits the budget
+        srv.submit_workload(w, 10)
+    assert e.value.code == lbm.LBM_ENOMEM
+    with pytest.raises(lbm.LbmError) as e:   # format mismatch
+        p = lbm.make_params(storage="f32")
+        srv.submit(w.shape, w.ns, w.rho, p, 10)
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        srv.poll(987654321)
+    assert e.value.code == lbm.LBM_ENOTFOUND
+    srv.close()
+
+
+def test_server_many_small_requests_complete():
+    srv = lbm.Server(storage="bf16s", max_slots=16, steps_per_tick=20, max_cells=32 ** 3)
+    ts = [srv.submit_workload(inputs.porous_domain(16 + (k % 3) * 8, 6000 + k), 40 + 20 * (k % 4))
+          for k in range(40)]
+    t0 = time.time()
+    out = [srv.wait(t, 120.0) for t in ts]
+    st = srv.stats()
+    srv.close()
+    assert all(r is not None and r["status"] == 0 for r in out)
+    assert st["completed"] == 40 and st["cell_updates"] > 0
+    assert time.time() - t0 < 120
