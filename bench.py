@@ -119,6 +119,84 @@ def stream_copy_gbs(mib=2048, reps=10):
     return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
+def ensemble(storage="f16s", ndom=64, steps=100, warmup=10, seed=3000):
+    """Batched ensemble: ndom porous domains with edges drawn from
+    {32, 48, 64, 96, 128}, stepped together (one batched launch per step) and,
+    for comparison, one after the other with the single-domain kernel."""
+    import torch
+    from paper_2206_11524_amd import inputs, lbm
+
+    g = np.random.Generator(np.random.PCG64(seed))
+    edges = g.choice([32, 48, 64, 96, 128], size=ndom)
+    ws = [inputs.porous_domain(int(e), seed + 1 + k) for k, e in enumerate(edges)]
+    cells = sum(w.ncells for w in ws)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sims = [lbm.from_workload(w, storage=storage) for w in ws]
+        grp = lbm.Group(sims)
+        grp.step(warmup)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        grp.step(steps)
+        stream.synchronize()
+        t_group = time.perf_counter() - t0
+        launch_ms = grp.last_step_ms()
+        t0 = time.perf_counter()
+        for sim in sims:
+            sim.step(steps)
+        stream.synchronize()
+        t_seq = time.perf_counter() - t0
+        grp.close()
+        for sim in sims:
+            sim.close()
+    del sims
+    torch.cuda.empty_cache()
+    return {"domains": ndom, "cells": cells, "storage": storage, "steps": steps,
+            "grouped_mlups": round(cells * steps / t_group / 1e6, 1),
+            "sequential_mlups": round(cells * steps / t_seq / 1e6, 1),
+            "grouped_launch_ms": round(launch_ms, 4),
+            "edges": {int(e): int((edges == e).sum()) for e in sorted(set(edges.tolist()))}}
+
+
+def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0):
+    """Continuous-batching serving: Poisson arrivals at `rate` per second for
+    `seconds`, each a porous domain of edge U{48..192} asking for U{2000..20000}
+    steps or convergence to 1e-6 relative momentum change; reports completion
+    latency percentiles and the aggregate MLUPS of the server."""
+    from paper_2206_11524_amd import inputs, lbm
+
+    g = np.random.Generator(np.random.PCG64(seed))
+    n = max(1, int(rate * seconds * 1.5) + 4)
+    gaps = g.exponential(1.0 / rate, size=n)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < seconds]
+    reqs = []
+    for k in range(len(arrivals)):
+        e = int(g.integers(48, 193))
+        reqs.append((inputs.porous_domain(e, seed + 1 + k), int(g.integers(2000, 20001))))
+    srv = lbm.Server(storage=storage, max_slots=64, steps_per_tick=steps_per_tick, max_cells=192 ** 3)
+    t0 = time.perf_counter()
+    tickets = []
+    depth = 0
+    for (w, steps), ta in zip(reqs, arrivals):
+        while time.perf_counter() - t0 < ta:
+            time.sleep(0.002)
+        tickets.append(srv.submit_workload(w, steps, conv_tol=1e-6))
+        st = srv.stats()
+        depth = max(depth, st["queued"] + st["active"])
+    res = [srv.wait(t, drain_s) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    done = [r for r in res if r is not None and r["status"] == 0]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in done])
+    return {"rate_per_s": rate, "arrival_window_s": seconds, "requests": len(reqs), "completed": len(done),
+            "converged": int(sum(r["converged"] for r in done)), "storage": storage,
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
+            "aggregate_mlups": round(st["cell_updates"] / max(st["busy_seconds"], 1e-9) / 1e6, 1),
+            "max_in_system": depth, "ticks": st["ticks"]}
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The FP64 CPU oracle on the same workload, timed on the host cores for a
     bounded number of whole-domain steps."""
@@ -152,6 +230,9 @@ def main():
     ap.add_argument("--variants", default="f32,f16s,bf16s")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=0.25, help="arrivals per second (0: no serving run)")
+    ap.add_argument("--serve-seconds", type=float, default=40.0)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (counter calibration)")
     args = ap.parse_args()
@@ -212,6 +293,12 @@ def main():
     }
     if "f32" in results and "f16s" in results:
         line["fp16_gain_over_fp32"] = round(results["f16s"]["mlups"] / results["f32"]["mlups"], 3)
+    if not args.no_ensemble:
+        line["ensemble"] = ensemble()
+        print(f"# ensemble: {line['ensemble']}", file=sys.stderr, flush=True)
+    if args.serve_rate > 0:
+        line["serving"] = serving(args.serve_rate, args.serve_seconds)
+        print(f"# serving: {line['serving']}", file=sys.stderr, flush=True)
     copy = stream_copy_gbs()
     line["stream_copy_GBs"] = round(copy, 1)
     line["roofline"]["frac_of_stream_copy"] = round(head["roofline"]["achieved"] / copy, 4)
