@@ -156,7 +156,8 @@ hm::BatchDomain domain_of(const lbm_ctx* c, int steps)
 {
     hm::BatchDomain d{};
     d.prob = c->prob;
-    d.zchunk = c->launch.zchunk;
+    // many domains share the GPU, so chunks stay long (few halo planes)
+    d.zchunk = std::min(c->prob.nz, std::max(32, c->launch.zchunk));
     d.buf[0] = c->buf[0];
     d.buf[1] = c->buf[1];
     d.ns = c->ns;

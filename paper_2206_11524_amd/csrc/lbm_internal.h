@@ -36,7 +36,7 @@ inline ScratchLayout scratch_layout(int64_t N, int ncomp)
 int validate(const lbm_domain* d, const lbm_params* p);
 int env_int(const char* name, int dflt);
 hm::Problem make_problem(const lbm_domain* d, const lbm_params* p);
-hm::Launch choose_launch(const hm::Problem& p);
+hm::Launch choose_launch(const hm::Problem& p, int cus);
 
 }  // namespace hm_rt
 

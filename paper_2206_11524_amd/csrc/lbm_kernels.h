@@ -32,8 +32,8 @@ struct Problem {
 };
 
 struct Launch {
-    int tile_x;   // cells per tile row (32 or 64)
-    int tile_y;   // rows per tile (4, 8 or 16 with 32-wide rows)
+    int tile_x;   // cells per tile row (32, 64 or 128)
+    int tile_y;   // rows per tile (4 with 128-wide rows; 4 or 8 with 64; 4, 8 or 16 with 32)
     int zchunk;   // planes per block
 };
 

@@ -21,6 +21,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace hm {
 
 // ---------------------------------------------------------------------------
@@ -293,15 +295,21 @@ __device__ __forceinline__ void stencil(const V* pm, const V* p0, const V* pp, i
 // column of cells; threads [s*TX*TY, (s+1)*TX*TY) handle component s.  The two
 // components of a cell meet only through LDS (densities and first moments),
 // which halves the registers per thread and doubles the waves per CU.
+//
+// LDS holds four density / n_s plane slots (plane p in slot p mod 4) and three
+// first-moment slots (p mod 3), so one barrier per plane suffices: a wave that
+// runs ahead into staging plane z+2 writes slots that no wave still colliding
+// plane z reads, and every wave has left the collision of plane z-1 before the
+// barrier that precedes the collision of plane z.
 template <typename ST, int NC, int CNS, int TX, int TY>
 struct TileShared {
     using T = typename ST::T;
     static constexpr int LW = TX + 2;
     static constexpr int LP = LW * (TY + 2);
     static constexpr int NTC = TX * TY;
-    T rho[3][NC][LP];
-    float ns[3][CNS][LP];
-    T j[NC][3][NTC];
+    T rho[4][NC][LP];
+    float ns[4][CNS][LP];
+    T j[3][NC][3][NTC];
 };
 
 // The sweep of one tile column (logical tile index L of the domain described
@@ -345,7 +353,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
 
     // ring cell of this thread (if any): top row, bottom row, left, right column
     const int ring_n = 2 * (TXe + 2) + 2 * TYe;
-    const bool ring = tl < ring_n;
+    const bool ring = NC == 2 && tl < ring_n;  // only the cohesion stencil reads ring densities
     int rlx, rly;
     {
         const int r = min(tl, ring_n - 1);
@@ -420,17 +428,17 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                 for (int c = 0; c < CNS; ++c) s_ns[slot][c][ns_lds[k]] = nsp[static_cast<size_t>(c) * a.N + ns_off[k]];
     };
     // first moment of the cell's component, published for the partner thread
-    auto publish_j = [&](const T h[kQ]) {
+    auto publish_j = [&](int js, const T h[kQ]) {
         if (act && NC == 2) {
-            s_j[s][0][tl] = first_moment<T, 0>(h);
-            s_j[s][1][tl] = first_moment<T, 1>(h);
-            s_j[s][2][tl] = first_moment<T, 2>(h);
+            s_j[js][s][0][tl] = first_moment<T, 0>(h);
+            s_j[js][s][1][tl] = first_moment<T, 1>(h);
+            s_j[js][s][2][tl] = first_moment<T, 2>(h);
         }
     };
 
     // Collision of plane z of this thread's component from h (pre-collision,
     // shifted) and the LDS slots of planes z-1, z, z+1.
-    auto collide = [&](int z, int sm, int s0, int sp, const T h[kQ]) {
+    auto collide = [&](int z, int sm, int s0, int sp, int js, const T h[kQ]) {
         if (!act) return;
         // common velocity, first term of Eq. (SC_u_eq), in component order
         T rho = 0, den = 0, num[3] = {0, 0, 0};
@@ -444,9 +452,9 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                 jc[1] = first_moment<T, 1>(h);
                 jc[2] = first_moment<T, 2>(h);
             } else {
-                jc[0] = s_j[c][0][tl];
-                jc[1] = s_j[c][1][tl];
-                jc[2] = s_j[c][2][tl];
+                jc[0] = s_j[js][c][0][tl];
+                jc[1] = s_j[js][c][1][tl];
+                jc[2] = s_j[js][c][2][tl];
             }
             if (c == s) rho_own = rc;
             rho += rc;
@@ -460,7 +468,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
         T ga[3];
         stencil<T, float, LW>(s_ns[sm][cn], s_ns[s0][cn], s_ns[sp][cn], me, ga);
         T gi[3] = {0, 0, 0};
-        if (NC == 2) stencil<T, T, LW>(s_rho[sm][1 - s], s_rho[s0][1 - s], s_rho[sp][1 - s], me, gi);
+        if constexpr (NC == 2) stencil<T, T, LW>(s_rho[sm][1 - s], s_rho[s0][1 - s], s_rho[sp][1 - s], me, gi);
         // force per unit density F_tot,s / rho_s (Eqs. SC_F_inter, SC_F_ads,
         // SC_F_ext); no shift for an absent component
         const bool present = rho_own > T(0);
@@ -508,36 +516,27 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     T hA[kQ];
     T hB[kQ];
 
-    // prologue: plane zs-1 (densities only, into slot 0), plane zs (kept in hA)
-    stage_plane(wrapz(zs - 1), 0, hB);
-    stage_plane(zs, 1, hA);
+    // plane p (zs-1 <= p <= ze) uses density slot (p - zs + 1) mod 4 and
+    // first-moment slot (p - zs) mod 3
+    auto rslot = [&](int p) { return (p - zs + 1) & 3; };
+    auto jslot = [&](int p) { return (p - zs) % 3; };
 
-    // sweep, two planes per iteration so the register sets alternate roles;
-    // slots (sm, s0, sp) hold planes (z-1, z, z+1)
-    int sm = 0, s0 = 1, sp = 2;
-    int z = zs;
-    for (; z + 1 < ze; z += 2) {
-        stage_plane(wrapz(z + 1), sp, hB);
-        publish_j(hA);
+    // prologue: plane zs-1 (densities only), plane zs (kept in hA)
+    stage_plane(wrapz(zs - 1), rslot(zs - 1), hB);
+    stage_plane(zs, rslot(zs), hA);
+    publish_j(jslot(zs), hA);
+
+    // sweep, two planes per iteration so the register sets alternate roles
+    for (int z = zs; z < ze; z += 2) {
+        stage_plane(wrapz(z + 1), rslot(z + 1), hB);
+        publish_j(jslot(z + 1), hB);
         __syncthreads();
-        collide(z, sm, s0, sp, hA);
+        collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hA);
+        if (z + 1 >= ze) break;
+        stage_plane(wrapz(z + 2), rslot(z + 2), hA);
+        publish_j(jslot(z + 2), hA);
         __syncthreads();
-        stage_plane(wrapz(z + 2), sm, hA);  // slot of z-1 is free again
-        publish_j(hB);
-        __syncthreads();
-        collide(z + 1, s0, sp, sm, hB);
-        __syncthreads();
-        // planes z+1, z+2 now sit in slots sp, sm; s0 is free for z+3
-        const int t0 = sm;
-        sm = sp;
-        sp = s0;
-        s0 = t0;
-    }
-    if (z < ze) {
-        stage_plane(wrapz(z + 1), sp, hB);
-        publish_j(hA);
-        __syncthreads();
-        collide(z, sm, s0, sp, hA);
+        collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), jslot(z + 1), hB);
     }
 }
 
@@ -557,6 +556,7 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
 }
 
 
+// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Batched step: the tiles of many domains in one launch.  The device table
 // holds a header and one entry per domain (geometry, parameters, ping-pong
@@ -806,7 +806,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
 
 bool tile_supported(int tx, int ty)
 {
-    return (tx == 64 && (ty == 4 || ty == 8)) || (tx == 32 && (ty == 4 || ty == 8 || ty == 16));
+    return (tx == 128 && ty == 4) || (tx == 64 && (ty == 4 || ty == 8)) || (tx == 32 && (ty == 4 || ty == 8 || ty == 16));
 }
 
 int storage_bytes(int storage)
@@ -842,6 +842,7 @@ template <typename ST, int NC, int CNS>
 static hipError_t step_ty(const Problem& p, const Launch& l, const void* A, void* B, const float* ns,
                           hipStream_t st)
 {
+    if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4>(p, l, A, B, ns, st);
     if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4>(p, l, A, B, ns, st);
     if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8>(p, l, A, B, ns, st);
     if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4>(p, l, A, B, ns, st);

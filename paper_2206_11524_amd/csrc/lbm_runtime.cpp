@@ -87,7 +87,7 @@ int env_int(const char* name, int dflt)
     return std::atoi(v);
 }
 
-hm::Launch choose_launch(const hm::Problem& p)
+hm::Launch choose_launch(const hm::Problem& p, int cus)
 {
     hm::Launch l{};
     // FP64 with two components needs the smaller tile to stay within the
@@ -104,9 +104,12 @@ hm::Launch choose_launch(const hm::Problem& p)
     const int64_t cols = static_cast<int64_t>(ntx) * nty;
     int zc = env_int("LBM_ZCHUNK", 0);
     if (zc <= 0) {
-        // aim at >= 512 blocks, but keep the z-halo (2 planes per chunk) small
-        const int64_t want_chunks = std::max<int64_t>(1, (512 + cols - 1) / cols);
-        zc = static_cast<int>(std::max<int64_t>(32, (p.nz + want_chunks - 1) / want_chunks));
+        // One block fits a CU (registers), so aim at one z-chunk per CU and
+        // column: every block is resident from the start and none waits for
+        // a second round.  Chunks shorter than 16 planes would spend too much
+        // on their two halo planes.
+        const int64_t chunks = std::max<int64_t>(1, std::max(cus, 1) / cols);
+        zc = static_cast<int>(std::max<int64_t>(16, (p.nz + chunks - 1) / chunks));
     }
     l.zchunk = std::min(std::max(zc, 1), p.nz);
     return l;
@@ -224,13 +227,19 @@ int lbm_create(const lbm_domain* dom, const float* n_s, const double* rho_init, 
     c->dom = *dom;
     c->prm = *prm;
     c->prob = make_problem(dom, prm);
-    c->launch = choose_launch(c->prob);
+
     lbm_required_bytes(dom, prm, &c->sizes);
     c->sl = scratch_layout(N, prm->ncomp);
     c->stream = static_cast<hipStream_t>(stream);
     c->cur = 0;
     c->t = 0;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LBM_EDEVICE; }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+        delete c;
+        return LBM_EDEVICE;
+    }
+    c->launch = choose_launch(c->prob, cus);
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         lbm_destroy(c);
         return LBM_EDEVICE;
