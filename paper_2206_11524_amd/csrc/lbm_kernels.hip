@@ -291,6 +291,105 @@ __device__ __forceinline__ void stencil(const V* pm, const V* p0, const V* pp, i
     for (int d = 0; d < 3; ++d) g[d] = ax[d] * (T(1) / T(18)) + dg[d] * (T(1) / T(36));
 }
 
+// Per-cell physics shared by the step kernels: every kernel evaluates the
+// same expressions, so the result of a cell does not depend on which kernel
+// or launch shape updated it.
+
+// Equilibrium velocity of component s at one cell, Eq. (SC_u_eq): the common
+// velocity sum_c (j_c / tau_c) / sum_c (rho_c / tau_c) plus tau_s F_tot,s /
+// rho_s, with F_tot,s the sum of Eqs. (SC_F_inter), (SC_F_ads) and
+// (SC_F_ext); no force shift for an absent component.  rho_m/0/p point at the
+// LDS density planes z-1, z, z+1 ([NC][LP]), ns_m/0/p at the n_s planes
+// ([CNS][LP]); me is the cell's LDS index and jc[c] the first moment of
+// component c at the cell.  Also returns the own density and n_s.
+template <typename T, int NC, int CNS, int LW, int LP>
+__device__ __forceinline__ void cell_velocity(const Args<T>& a, int s, int me, const T* rho_m, const T* rho_0,
+                                              const T* rho_p, const float* ns_m, const float* ns_0,
+                                              const float* ns_p, const T (&jc)[NC][3], T ueq[3], T& rho_own, T& n)
+{
+    T rho = 0, den = 0, num[3] = {0, 0, 0};
+    rho_own = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const T rc = rho_0[c * LP + me];
+        if (c == s) rho_own = rc;
+        rho += rc;
+        den += rc * a.inv_tau[c];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) num[d] += jc[c][d] * a.inv_tau[c];
+    }
+    const T inv_den = den > T(0) ? T(1) / den : T(0);
+    const T inv_rho = rho > T(0) ? T(1) / rho : T(0);
+    const int cn = CNS == 2 ? s : 0;
+    T ga[3];
+    stencil<T, float, LW>(ns_m + cn * LP, ns_0 + cn * LP, ns_p + cn * LP, me, ga);
+    T gi[3] = {0, 0, 0};
+    if constexpr (NC == 2) stencil<T, T, LW>(rho_m + (1 - s) * LP, rho_0 + (1 - s) * LP, rho_p + (1 - s) * LP, me, gi);
+    const bool present = rho_own > T(0);
+    const T tau_s = a.tau[s], Gads = a.Gads_s[s];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T acc = -a.G_s * gi[d] - Gads * ga[d] + a.F[d] * inv_rho;
+        ueq[d] = num[d] * inv_den + (present ? tau_s * acc : T(0));
+    }
+    n = static_cast<T>(ns_0[cn * LP + me]);
+}
+
+// Force-shifted BGK collision blended with partial bounce-back, Eq. (LGS), in
+// the shifted variables: post_i = (1-n)(h_i - (h_i - h^eq_i)/tau_s) + n h_ibar
+// with h^eq from Eq. (Maxwell) at u_eq (the w_i rho0 shift cancels because
+// w_ibar = w_i).  relax_coef gathers the per-cell factors, relax_dir gives the
+// results of one direction pair (i, i+9), relax_rest that of direction 0.
+template <typename T>
+struct RelaxCoef {
+    T ca, n;                  // weights of h_i and h_ibar
+    T K0[3], K1[3], K2[3];    // weight of h^eq_i: K0 + K1 c.u + K2 (c.u)^2 per weight class
+    T u[3];
+};
+
+template <typename T>
+__device__ __forceinline__ RelaxCoef<T> relax_coef(const Args<T>& a, int s, T rho_own, const T ueq[3], T n)
+{
+    RelaxCoef<T> k;
+    const T uu = ueq[0] * ueq[0] + ueq[1] * ueq[1] + ueq[2] * ueq[2];
+    const T omn = T(1) - n;
+    const T cb = omn * a.inv_tau[s];  // weight of h^eq
+    k.ca = omn - cb;                  // weight of h
+    k.n = n;
+    const T base0 = (rho_own - a.rho0[s]) - T(1.5) * rho_own * uu;
+    const T r3 = T(3) * rho_own, r45 = T(4.5) * rho_own;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T wk = cb * (c == 0 ? T(1) / T(3) : (c == 1 ? T(1) / T(18) : T(1) / T(36)));
+        k.K0[c] = wk * base0;
+        k.K1[c] = wk * r3;
+        k.K2[c] = wk * r45;
+        k.u[c] = ueq[c];
+    }
+    return k;
+}
+
+template <typename T>
+__device__ __forceinline__ T relax_rest(const RelaxCoef<T>& k, T h0)
+{
+    return k.ca * h0 + k.n * h0 + k.K0[0];
+}
+
+// i in 1..9: hi = h_i, ho = h_{i+9}
+template <typename T>
+__device__ __forceinline__ void relax_dir(const RelaxCoef<T>& k, int i, T hi, T ho, T& post_i, T& post_o)
+{
+    const int c = (CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]) == 1 ? 1 : 2;
+    T cu = T(0);
+    if (CX[i]) cu += CX[i] > 0 ? k.u[0] : -k.u[0];
+    if (CY[i]) cu += CY[i] > 0 ? k.u[1] : -k.u[1];
+    if (CZ[i]) cu += CZ[i] > 0 ? k.u[2] : -k.u[2];
+    const T t = k.K2[c] * (cu * cu) + k.K0[c];
+    const T e = k.K1[c] * cu;
+    post_i = k.ca * hi + (k.n * ho + (t + e));
+    post_o = k.ca * ho + (k.n * hi + (t - e));
+}
+
 // One thread per (cell, component): a block of NC*TX*TY threads owns a TX x TY
 // column of cells; threads [s*TX*TY, (s+1)*TX*TY) handle component s.  The two
 // components of a cell meet only through LDS (densities and first moments),
@@ -407,12 +506,20 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
             for (int i = 0; i < kQ; ++i) h[i] = wgt<T>(i) * dr;
         }
     };
-    // densities of plane p: own cell into h, ring cell pulled here; n_s plane
-    auto stage_plane = [&](int p, int slot, T h[kQ]) {
+
+    // Stage plane p into LDS slot `slot`: densities of the own cell and of
+    // the ring cell, first moments of the own cell (slot js, none if js < 0),
+    // n_s; the own cell's populations stay in h for the collision.
+    auto stage_plane = [&](int p, int slot, int js, T h[kQ]) {
         if (act) {
             pull_plane(p, qme, h);
             reservoir_override(reservoir_of(a, x, y, p), h);
             s_rho[slot][s][me] = a.rho0[s] + sum19(h);
+            if (NC == 2 && js >= 0) {
+                s_j[js][s][0][tl] = first_moment<T, 0>(h);
+                s_j[js][s][1][tl] = first_moment<T, 1>(h);
+                s_j[js][s][2][tl] = first_moment<T, 2>(h);
+            }
         }
         if (ring) {
             T hr[kQ];
@@ -427,89 +534,35 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
 #pragma unroll
                 for (int c = 0; c < CNS; ++c) s_ns[slot][c][ns_lds[k]] = nsp[static_cast<size_t>(c) * a.N + ns_off[k]];
     };
-    // first moment of the cell's component, published for the partner thread
-    auto publish_j = [&](int js, const T h[kQ]) {
-        if (act && NC == 2) {
-            s_j[js][s][0][tl] = first_moment<T, 0>(h);
-            s_j[js][s][1][tl] = first_moment<T, 1>(h);
-            s_j[js][s][2][tl] = first_moment<T, 2>(h);
-        }
-    };
 
     // Collision of plane z of this thread's component from h (pre-collision,
     // shifted) and the LDS slots of planes z-1, z, z+1.
     auto collide = [&](int z, int sm, int s0, int sp, int js, const T h[kQ]) {
         if (!act) return;
-        // common velocity, first term of Eq. (SC_u_eq), in component order
-        T rho = 0, den = 0, num[3] = {0, 0, 0};
-        T rho_own = 0;
+        T jc[NC][3];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const T rc = s_rho[s0][c][me];
-            T jc[3];
-            if (NC == 1) {
-                jc[0] = first_moment<T, 0>(h);
-                jc[1] = first_moment<T, 1>(h);
-                jc[2] = first_moment<T, 2>(h);
+            if constexpr (NC == 1) {
+                jc[c][0] = first_moment<T, 0>(h);
+                jc[c][1] = first_moment<T, 1>(h);
+                jc[c][2] = first_moment<T, 2>(h);
             } else {
-                jc[0] = s_j[js][c][0][tl];
-                jc[1] = s_j[js][c][1][tl];
-                jc[2] = s_j[js][c][2][tl];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) jc[c][d] = s_j[js][c][d][tl];
             }
-            if (c == s) rho_own = rc;
-            rho += rc;
-            den += rc * a.inv_tau[c];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) num[d] += jc[d] * a.inv_tau[c];
         }
-        const T inv_den = den > T(0) ? T(1) / den : T(0);
-        const T inv_rho = rho > T(0) ? T(1) / rho : T(0);
-        const int cn = CNS == 2 ? s : 0;
-        T ga[3];
-        stencil<T, float, LW>(s_ns[sm][cn], s_ns[s0][cn], s_ns[sp][cn], me, ga);
-        T gi[3] = {0, 0, 0};
-        if constexpr (NC == 2) stencil<T, T, LW>(s_rho[sm][1 - s], s_rho[s0][1 - s], s_rho[sp][1 - s], me, gi);
-        // force per unit density F_tot,s / rho_s (Eqs. SC_F_inter, SC_F_ads,
-        // SC_F_ext); no shift for an absent component
-        const bool present = rho_own > T(0);
-        const T tau_s = a.tau[s], inv_tau_s = a.inv_tau[s], Gads = a.Gads_s[s];
-        T ueq[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T acc = -a.G_s * gi[d] - Gads * ga[d] + a.F[d] * inv_rho;
-            ueq[d] = num[d] * inv_den + (present ? tau_s * acc : T(0));
-        }
-        const T uu = ueq[0] * ueq[0] + ueq[1] * ueq[1] + ueq[2] * ueq[2];
-        const T n = static_cast<T>(s_ns[s0][cn][me]);
-        const T omn = T(1) - n;
-        const T cb = omn * inv_tau_s;  // weight of h^eq
-        const T ca = omn - cb;         // weight of h
-        // cb*h^eq_i = K0 + K1 cu + K2 cu^2 per weight class
-        const T base0 = (rho_own - a.rho0[s]) - T(1.5) * rho_own * uu;
-        const T r3 = T(3) * rho_own, r45 = T(4.5) * rho_own;
-        T K0[3], K1[3], K2[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T wk = cb * (k == 0 ? T(1) / T(3) : (k == 1 ? T(1) / T(18) : T(1) / T(36)));
-            K0[k] = wk * base0;
-            K1[k] = wk * r3;
-            K2[k] = wk * r45;
-        }
+        T ueq[3], rho_own, n;
+        cell_velocity<T, NC, CNS, LW, LP>(a, s, me, &s_rho[sm][0][0], &s_rho[s0][0][0], &s_rho[sp][0][0],
+                                          &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, ueq, rho_own, n);
         const uint32_t zo = static_cast<uint32_t>(z) * plane_bytes;
-        ST::bst(ST::enc(ca * h[0] + n * h[0] + K0[0], a.scale), rb, own, zo);
+        const RelaxCoef<T> k = relax_coef<T>(a, s, rho_own, ueq, n);
+        ST::bst(ST::enc(relax_rest(k, h[0]), a.scale), rb, own, zo);
 #pragma unroll
         for (int i = 1; i <= 9; ++i) {
-            const int k = (CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]) == 1 ? 1 : 2;
-            T cu = T(0);
-            if (CX[i]) cu += CX[i] > 0 ? ueq[0] : -ueq[0];
-            if (CY[i]) cu += CY[i] > 0 ? ueq[1] : -ueq[1];
-            if (CZ[i]) cu += CZ[i] > 0 ? ueq[2] : -ueq[2];
-            const T t = K2[k] * (cu * cu) + K0[k];
-            const T e = K1[k] * cu;
-            const T post_i = ca * h[i] + (n * h[i + 9] + (t + e));
-            const T post_o = ca * h[i + 9] + (n * h[i] + (t - e));
-            ST::bst(ST::enc(post_i, a.scale), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
-            ST::bst(ST::enc(post_o, a.scale), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
+            T pi, po;
+            relax_dir(k, i, h[i], h[i + 9], pi, po);
+            ST::bst(ST::enc(pi, a.scale), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
+            ST::bst(ST::enc(po, a.scale), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
         }
     };
 
@@ -522,19 +575,16 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     auto jslot = [&](int p) { return (p - zs) % 3; };
 
     // prologue: plane zs-1 (densities only), plane zs (kept in hA)
-    stage_plane(wrapz(zs - 1), rslot(zs - 1), hB);
-    stage_plane(zs, rslot(zs), hA);
-    publish_j(jslot(zs), hA);
+    stage_plane(wrapz(zs - 1), rslot(zs - 1), -1, hB);
+    stage_plane(zs, rslot(zs), jslot(zs), hA);
 
     // sweep, two planes per iteration so the register sets alternate roles
     for (int z = zs; z < ze; z += 2) {
-        stage_plane(wrapz(z + 1), rslot(z + 1), hB);
-        publish_j(jslot(z + 1), hB);
+        stage_plane(wrapz(z + 1), rslot(z + 1), jslot(z + 1), hB);
         __syncthreads();
         collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hA);
         if (z + 1 >= ze) break;
-        stage_plane(wrapz(z + 2), rslot(z + 2), hA);
-        publish_j(jslot(z + 2), hA);
+        stage_plane(wrapz(z + 2), rslot(z + 2), jslot(z + 2), hA);
         __syncthreads();
         collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), jslot(z + 1), hB);
     }

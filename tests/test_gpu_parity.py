@@ -207,6 +207,27 @@ def test_launch_configuration_does_not_change_results(monkeypatch):
     assert all(v == 0.0 for v in diffs.values()), diffs
 
 
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+@pytest.mark.parametrize("shape", [(98, 30, 37), (130, 9, 11), (24, 17, 13)])
+def test_tile_width_does_not_change_16bit_results(monkeypatch, storage, shape):
+    """With 16-bit storage too, 64- and 32-cell tile rows (different ring,
+    halo and block decomposition) give identical bits, also for ragged tiles,
+    rows shorter than a tile and a reservoir slab across x."""
+    w = inputs.random_state(shape, 31, ns_choices=[0.0, 0.4, 1.0], rho_range=(0.3, 0.7))
+    w.G, w.G_ads, w.F_ext = 0.7, (0.2, -0.2), (1e-4, 2e-4, -1e-4)
+    w.reservoirs = [(0, 0, 2, (0.6, 0.35))]
+    outs = []
+    for tx in (64, 32):
+        monkeypatch.setenv("LBM_TILE_X", str(tx))
+        monkeypatch.setenv("LBM_TILE_Y", "8")
+        sim = lbm.from_workload(w, storage=storage)
+        sim.step(9)
+        outs.append(sim.populations())
+        sim.close()
+    assert np.isfinite(outs[0]).all()
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
 def test_checkpoint_restart_is_bitwise(storage):
     w = inputs.droplet(n=24, radius=6)
