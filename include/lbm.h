@@ -43,13 +43,26 @@ extern "C" {
 
 /* Storage format of the populations.  Arithmetic is FP64 for LBM_F64 and FP32
  * otherwise.  Stored value h = (f_i - w_i*rho_shift[s]) * 2^store_scale_log2,
- * rounded to nearest even for the 16-bit formats. */
+ * rounded as lbm_params.rounding says for the 16-bit formats. */
 typedef enum {
     LBM_F64 = 0,
     LBM_F32 = 1,
     LBM_F16S = 2,  /* IEEE binary16, shifted   */
     LBM_BF16S = 3  /* bfloat16, shifted        */
 } lbm_storage;
+
+/* Rounding of the 16-bit formats (FP32 and FP64 always round to nearest).
+ * Stochastic rounding takes the upper neighbour with probability equal to the
+ * dropped fraction, so it is unbiased: changes smaller than half a unit in the
+ * last place survive on average instead of being rounded away every step (a
+ * slowly developing flow otherwise stalls short of its steady state).  Its
+ * random bits are a hash (MurmurHash3 32-bit finaliser) of the cell index,
+ * component, direction and time step, so results are reproducible bit for bit
+ * and do not depend on the launch decomposition. */
+typedef enum {
+    LBM_ROUND_NEAREST = 0,   /* round to nearest, ties to even */
+    LBM_ROUND_STOCHASTIC = 1
+} lbm_rounding;
 
 typedef struct {
     int32_t nx, ny, nz;
@@ -80,6 +93,8 @@ typedef struct {
     int32_t store_scale_log2; /* power-of-two scale of stored values (16-bit formats)   */
     int32_t n_res;            /* number of reservoirs, 0..LBM_MAX_RES                   */
     int32_t check_every;      /* health check (finite mass) every k steps; 0 = never    */
+    int32_t rounding;         /* lbm_rounding (16-bit formats)                          */
+    int32_t pad;
     lbm_reservoir res[LBM_MAX_RES];
 } lbm_params;
 
@@ -151,9 +166,14 @@ int lbm_totals_get(lbm_ctx* ctx, lbm_totals* tot);
  * Reservoir cells hold their prescribed equilibrium.  Synchronises. */
 int lbm_get_populations(lbm_ctx* ctx, double* f);
 
-/* Replace the state by canonical populations f [ncomp*19*N] (rounded to the
- * storage format).  The time counter is kept.  Synchronises. */
+/* Replace the state by canonical populations f [ncomp*19*N] (rounded to
+ * nearest in the storage format).  The time counter is kept.  Synchronises. */
 int lbm_set_populations(lbm_ctx* ctx, const double* f);
+
+/* Set the time counter (t >= 0), e.g. to resume a checkpoint taken at time t:
+ * stochastic rounding draws on the time step, so a resumed run repeats the
+ * original bit for bit only from the same t. */
+int lbm_set_time(lbm_ctx* ctx, int64_t t);
 
 /* Change the prescribed densities of reservoir r (e.g. a rising inlet density,
  * Sec. 4) from the next step on. */
@@ -232,7 +252,10 @@ typedef struct {
     lbm_params params;        /* storage, ncomp and c_ns must match the server               */
     int64_t max_steps;        /* run at most this many steps (>= 1)                          */
     double conv_tol;          /* stop when |J(t) - J(t-K)| <= conv_tol |J(t)|, K = steps_per_tick;
-                                 0 disables                                                  */
+                                 0 disables.  With stochastic rounding J carries the rounding
+                                 noise of the 16-bit state, so the tolerance must lie above
+                                 it; with rounding to nearest the test also fires where the
+                                 rounded state stops changing before the flow has settled    */
     double* rho_out;          /* optional caller buffer [ncomp][N] for the final densities;
                                  must stay valid until the result is final                   */
 } lbm_request;

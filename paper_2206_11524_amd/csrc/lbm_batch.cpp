@@ -162,6 +162,7 @@ hm::BatchDomain domain_of(const lbm_ctx* c, int steps)
     d.buf[1] = c->buf[1];
     d.ns = c->ns;
     d.parity = c->cur;
+    d.t = c->t;
     d.steps = steps;
     return d;
 }

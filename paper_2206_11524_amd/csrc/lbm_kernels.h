@@ -25,6 +25,7 @@ struct Problem {
     double F[3];
     double rho0[2];
     double scale;      // 2^store_scale_log2
+    int stochastic;    // 16-bit formats: stochastic rounding of stored values
     double g_scale, G_inter;
     int n_res;
     int res_axis[kMaxRes], res_lo[kMaxRes], res_hi[kMaxRes];
@@ -43,8 +44,9 @@ bool tile_supported(int tile_x, int tile_y);
 // Bytes per stored population.
 int storage_bytes(int storage);
 
-// One time step A -> B (pull streaming, fused forces/collision/bounce-back).
-hipError_t launch_step(const Problem& p, const Launch& l, const void* A, void* B,
+// One time step A -> B (pull streaming, fused forces/collision/bounce-back);
+// t is the time step of the state in A (keys the stochastic rounding).
+hipError_t launch_step(const Problem& p, const Launch& l, int64_t t, const void* A, void* B,
                        const float* ns, hipStream_t s);
 
 // t = 0 state: rest equilibrium of rho_init (device FP64 [ncomp][N]).
@@ -81,6 +83,7 @@ struct BatchDomain {
     const void* buf[2];  // population buffers (ping-pong)
     const float* ns;
     int parity;          // buffer holding the state before the first launch of the tick
+    int64_t t;           // time step of that state
     int steps;           // launches k = 0 .. steps-1 of the tick advance this domain
 };
 

@@ -63,6 +63,7 @@ struct F64 {
     using T = double;
     static __device__ __forceinline__ T dec(E v, T) { return v; }
     static __device__ __forceinline__ E enc(T v, T) { return v; }
+    static __device__ __forceinline__ E enc_sr(T v, T, uint32_t) { return v; }  // rounds to nearest
     static __device__ __forceinline__ E bld(rsrc_t r, uint32_t vo, uint32_t so)
     {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
@@ -77,6 +78,7 @@ struct F32 {
     using T = float;
     static __device__ __forceinline__ T dec(E v, T) { return v; }
     static __device__ __forceinline__ E enc(T v, T) { return v; }
+    static __device__ __forceinline__ E enc_sr(T v, T, uint32_t) { return v; }  // rounds to nearest
     static __device__ __forceinline__ E bld(rsrc_t r, uint32_t vo, uint32_t so)
     {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
@@ -107,6 +109,24 @@ struct F16 : Half16 {
     {
         return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v * scale));
     }
+    // Stochastic rounding with 16 random bits r16: the value rounds up with
+    // probability equal to its fraction of the binary16 spacing.  Add 13
+    // random bits below the spacing to the FP32 magnitude and cut them.
+    // Magnitudes below 2^-14 are first lifted by 2^-14 into the binade
+    // [2^-14, 2^-13), whose spacing 2^-24 is that of the binary16 subnormals,
+    // and lowered again afterwards (exact); the lift itself rounds by at most
+    // 2^-13 of a spacing.  Inf and NaN keep their class; beyond the binary16
+    // range the conversion gives inf as rounding to nearest does.
+    static __device__ __forceinline__ E enc_sr(T v, T scale, uint32_t r16)
+    {
+        const uint32_t u = __float_as_uint(v * scale);
+        const uint32_t sign = u & 0x80000000u;
+        const float ax = __uint_as_float(u ^ sign);
+        const float lift = ax < 0x1p-14f ? 0x1p-14f : 0.0f;
+        const uint32_t q = (__float_as_uint(ax + lift) + (r16 >> 3)) & ~0x1fffu;
+        const float y = __uint_as_float(q) - lift;
+        return __builtin_bit_cast(uint16_t, static_cast<_Float16>(__uint_as_float(__float_as_uint(y) | sign)));
+    }
 };
 struct BF16 : Half16 {
     using E = uint16_t;
@@ -122,7 +142,40 @@ struct BF16 : Half16 {
         u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
         return static_cast<E>(u >> 16);
     }
+    // Stochastic rounding: 16 random bits added below the kept bits before
+    // truncation.
+    static __device__ __forceinline__ E enc_sr(T v, T scale, uint32_t r16)
+    {
+        uint32_t u = __float_as_uint(v * scale);
+        if ((u & 0x7f800000u) == 0x7f800000u) return enc(v, scale);
+        u += r16;
+        return static_cast<E>(u >> 16);
+    }
 };
+
+// MurmurHash3's 32-bit finaliser (Appleby): a bijective avalanche mixer; the
+// random bits of the stochastic rounding are fmix32 of a counter built from
+// cell, component, direction and time step.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+constexpr uint32_t kGolden = 0x9e3779b9u;
+
+// Marsaglia's xorshift32 step (shifts 13, 17, 5): the following random words
+// of one cell, after fmix32 has seeded them.
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x)
+{
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
 
 // Kernel parameters in the arithmetic type.
 template <typename T>
@@ -135,6 +188,8 @@ struct Args {
     T F[3];
     T rho0[2];
     T scale, inv_scale;
+    int sr;      // stochastic rounding of stored values
+    uint32_t t;  // time step of the state read by the launch (single-domain launches)
     int n_res;
     int res_axis[kMaxRes], res_lo[kMaxRes], res_hi[kMaxRes];
     T res_dr[kMaxRes][2];  // rho_res - rho0, shifted density of the reservoir
@@ -156,6 +211,8 @@ static Args<T> make_args(const Problem& p)
     for (int d = 0; d < 3; ++d) a.F[d] = static_cast<T>(p.F[d]);
     a.scale = static_cast<T>(p.scale);
     a.inv_scale = static_cast<T>(1.0 / p.scale);
+    a.sr = p.stochastic;
+    a.t = 0;
     a.n_res = p.n_res;
     for (int r = 0; r < kMaxRes; ++r) {
         a.res_axis[r] = p.res_axis[r];
@@ -416,7 +473,7 @@ struct TileShared {
 template <typename ST, int NC, int CNS, int TX, int TY>
 __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const typename ST::E* __restrict__ A,
                                           typename ST::E* __restrict__ B, const float* __restrict__ ns, int L,
-                                          TileShared<ST, NC, CNS, TX, TY>& sh)
+                                          uint32_t t, TileShared<ST, NC, CNS, TX, TY>& sh)
 {
     using T = typename ST::T;
     using E = typename ST::E;
@@ -485,6 +542,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     }
 
     auto wrapz = [&](int p) { return p < 0 ? p + a.nz : (p >= a.nz ? p - a.nz : p); };
+    const uint32_t t_key = fmix32(t ^ kGolden);  // stochastic rounding: time part of the counter
 
     const uint32_t dir_bytes = static_cast<uint32_t>(a.N * static_cast<int>(sizeof(E)));
     const uint32_t plane_bytes = static_cast<uint32_t>(plane * static_cast<int>(sizeof(E)));
@@ -556,13 +614,30 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                                           &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, ueq, rho_own, n);
         const uint32_t zo = static_cast<uint32_t>(z) * plane_bytes;
         const RelaxCoef<T> k = relax_coef<T>(a, s, rho_own, ueq, n);
-        ST::bst(ST::enc(relax_rest(k, h[0]), a.scale), rb, own, zo);
+        if (a.sr) {
+            // counter: (cell, component) mixed with the time step, then the direction
+            // 32 random bits per direction pair (i, i+9), 16 for each value:
+            // fmix32 of (cell, component, time), then xorshift32 steps
+            const uint32_t cell = static_cast<uint32_t>(z * plane + y * a.nx + x);
+            uint32_t r = fmix32(t_key ^ (2u * cell + static_cast<uint32_t>(s))) | 1u;  // nonzero state
+            ST::bst(ST::enc_sr(relax_rest(k, h[0]), a.scale, r >> 16), rb, own, zo);
 #pragma unroll
-        for (int i = 1; i <= 9; ++i) {
-            T pi, po;
-            relax_dir(k, i, h[i], h[i + 9], pi, po);
-            ST::bst(ST::enc(pi, a.scale), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
-            ST::bst(ST::enc(po, a.scale), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
+            for (int i = 1; i <= 9; ++i) {
+                T pi, po;
+                relax_dir(k, i, h[i], h[i + 9], pi, po);
+                r = xorshift32(r);
+                ST::bst(ST::enc_sr(pi, a.scale, r & 0xffffu), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
+                ST::bst(ST::enc_sr(po, a.scale, r >> 16), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
+            }
+        } else {
+            ST::bst(ST::enc(relax_rest(k, h[0]), a.scale), rb, own, zo);
+#pragma unroll
+            for (int i = 1; i <= 9; ++i) {
+                T pi, po;
+                relax_dir(k, i, h[i], h[i + 9], pi, po);
+                ST::bst(ST::enc(pi, a.scale), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
+                ST::bst(ST::enc(po, a.scale), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
+            }
         }
     };
 
@@ -602,7 +677,7 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
     const int nb = gridDim.x;
     int L = blockIdx.x;
     if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    step_tile<ST, NC, CNS, TX, TY>(a, A, B, ns, L, sh);
+    step_tile<ST, NC, CNS, TX, TY>(a, A, B, ns, L, a.t, sh);
 }
 
 
@@ -655,7 +730,7 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step_batch(const char* __restric
         const int cur = (e.parity + k) & 1;
         __syncthreads();  // the previous tile's LDS is no longer read
         step_tile<ST, NC, CNS, TX, TY>(e.a, static_cast<const E*>(e.buf[cur]), static_cast<E*>(const_cast<void*>(e.buf[1 - cur])),
-                                       e.ns, w - e.tile_begin, sh);
+                                       e.ns, w - e.tile_begin, e.a.t + static_cast<uint32_t>(k), sh);
     }
 }
 
@@ -871,7 +946,7 @@ int storage_bytes(int storage)
 }
 
 template <typename ST, int NC, int CNS, int TX, int TY>
-static hipError_t step_t(const Problem& p, const Launch& l, const void* A, void* B, const float* ns,
+static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
                          hipStream_t st)
 {
     using T = typename ST::T;
@@ -881,6 +956,7 @@ static hipError_t step_t(const Problem& p, const Launch& l, const void* A, void*
     a.ntx = (p.nx + TX - 1) / TX;
     a.nty = (p.ny + TY - 1) / TY;
     a.nzc = (p.nz + l.zchunk - 1) / l.zchunk;
+    a.t = static_cast<uint32_t>(t);
     const int nblocks = a.ntx * a.nty * a.nzc;
     hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY>), dim3(nblocks), dim3(NC * TX * TY), 0, st, a,
                        static_cast<const E*>(A), static_cast<E*>(B), ns);
@@ -889,35 +965,35 @@ static hipError_t step_t(const Problem& p, const Launch& l, const void* A, void*
 
 // Tile shapes (TX x TY cells per block) compiled in.
 template <typename ST, int NC, int CNS>
-static hipError_t step_ty(const Problem& p, const Launch& l, const void* A, void* B, const float* ns,
+static hipError_t step_ty(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
                           hipStream_t st)
 {
-    if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4>(p, l, A, B, ns, st);
-    if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4>(p, l, A, B, ns, st);
-    if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8>(p, l, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4>(p, l, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8>(p, l, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16>(p, l, A, B, ns, st);
+    if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16>(p, l, t, A, B, ns, st);
     return hipErrorInvalidValue;
 }
 
 template <typename ST>
-static hipError_t step_st(const Problem& p, const Launch& l, const void* A, void* B, const float* ns,
+static hipError_t step_st(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
                           hipStream_t st)
 {
-    if (p.ncomp == 1) return step_ty<ST, 1, 1>(p, l, A, B, ns, st);
-    if (p.c_ns == 1) return step_ty<ST, 2, 1>(p, l, A, B, ns, st);
-    return step_ty<ST, 2, 2>(p, l, A, B, ns, st);
+    if (p.ncomp == 1) return step_ty<ST, 1, 1>(p, l, t, A, B, ns, st);
+    if (p.c_ns == 1) return step_ty<ST, 2, 1>(p, l, t, A, B, ns, st);
+    return step_ty<ST, 2, 2>(p, l, t, A, B, ns, st);
 }
 
-hipError_t launch_step(const Problem& p, const Launch& l, const void* A, void* B, const float* ns,
+hipError_t launch_step(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
                        hipStream_t st)
 {
     switch (p.storage) {
-    case kF64: return step_st<F64>(p, l, A, B, ns, st);
-    case kF32: return step_st<F32>(p, l, A, B, ns, st);
-    case kF16: return step_st<F16>(p, l, A, B, ns, st);
-    case kBF16: return step_st<BF16>(p, l, A, B, ns, st);
+    case kF64: return step_st<F64>(p, l, t, A, B, ns, st);
+    case kF32: return step_st<F32>(p, l, t, A, B, ns, st);
+    case kF16: return step_st<F16>(p, l, t, A, B, ns, st);
+    case kBF16: return step_st<BF16>(p, l, t, A, B, ns, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1029,6 +1105,7 @@ static int batch_encode_t(const BatchDomain* d, int n, int tile_x, int tile_y, v
         a.ntx = (d[i].prob.nx + tile_x - 1) / tile_x;
         a.nty = (d[i].prob.ny + tile_y - 1) / tile_y;
         a.nzc = (d[i].prob.nz + a.zchunk - 1) / a.zchunk;
+        a.t = static_cast<uint32_t>(d[i].t);
         e[i].a = a;
         e[i].buf[0] = d[i].buf[0];
         e[i].buf[1] = d[i].buf[1];

@@ -47,6 +47,7 @@ int validate(const lbm_domain* d, const lbm_params* p)
             if (!std::isfinite(R.rho[s])) return LBM_EINVAL;
     }
     if (p->check_every < 0) return LBM_EINVAL;
+    if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -66,6 +67,7 @@ hm::Problem make_problem(const lbm_domain* d, const lbm_params* p)
     q.G_inter = p->G_inter;
     for (int a = 0; a < 3; ++a) q.F[a] = p->F_ext[a];
     q.scale = std::ldexp(1.0, p->store_scale_log2);
+    q.stochastic = (p->storage == LBM_F16S || p->storage == LBM_BF16S) && p->rounding == LBM_ROUND_STOCHASTIC;
     q.n_res = p->n_res;
     for (int r = 0; r < hm::kMaxRes; ++r) {
         if (r < p->n_res) {
@@ -281,7 +283,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps)
     if (nsteps == 0) return LBM_OK;
     HIP_TRY(hipEventRecord(c->ev0, c->stream));
     for (int64_t k = 0; k < nsteps; ++k) {
-        HIP_TRY(hm::launch_step(c->prob, c->launch, c->buf[c->cur], c->buf[1 - c->cur], c->ns, c->stream));
+        HIP_TRY(hm::launch_step(c->prob, c->launch, c->t, c->buf[c->cur], c->buf[1 - c->cur], c->ns, c->stream));
         c->cur = 1 - c->cur;
         c->t += 1;
         if (c->prm.check_every > 0 && c->t % c->prm.check_every == 0) {
@@ -370,6 +372,13 @@ int lbm_set_reservoir(lbm_ctx* c, int32_t r, const double rho[2])
 }
 
 int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+int lbm_set_time(lbm_ctx* c, int64_t t)
+{
+    if (!c || t < 0) return LBM_EINVAL;
+    c->t = t;
+    return LBM_OK;
+}
 
 int lbm_sync(lbm_ctx* c)
 {

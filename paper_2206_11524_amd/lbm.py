@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("G_inter", C.c_double), ("G_ads", C.c_double * 2), ("F_ext", C.c_double * 3),
                 ("g_scale", C.c_double), ("rho_shift", C.c_double * 2), ("storage", C.c_int32),
                 ("store_scale_log2", C.c_int32), ("n_res", C.c_int32), ("check_every", C.c_int32),
-                ("res", Reservoir * MAX_RES)]
+                ("rounding", C.c_int32), ("pad", C.c_int32), ("res", Reservoir * MAX_RES)]
 
 
 class Sizes(C.Structure):
@@ -72,6 +72,7 @@ SIGNATURES = {
     "lbm_set_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_set_reservoir": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "lbm_time": (C.c_int64, [C.c_void_p]),
+    "lbm_set_time": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_sync": (C.c_int, [C.c_void_p]),
     "lbm_last_step_ms": (C.c_double, [C.c_void_p]),
     "lbm_destroy": (None, [C.c_void_p]),
@@ -100,20 +101,29 @@ def _check(code: int, what: str):
 
 
 def default_shift(storage: str, ncomp: int, rho_init: np.ndarray):
-    """Shift rho0 for the stored populations: zero for the plain FP64/FP32
-    formats; for the 16-bit formats the smallest initial density of each
-    component (its dissolved density in a two-phase set-up), so populations of
-    a component where it is dilute are stored as small numbers with full
-    relative precision."""
-    if storage in ("f64", "f32"):
+    """Shift rho0 for the stored populations: zero for FP64; for FP32 and the
+    16-bit formats the smallest initial density of each component (its
+    dissolved density in a two-phase set-up), so the stored values are the
+    deviations f - w_i rho0, small where a component is dilute or the flow is
+    slow, and carry full relative precision."""
+    if storage == "f64":
         return (0.0, 0.0)
     out = [float(rho_init[s].min()) for s in range(ncomp)]
     return tuple(out + [0.0] * (2 - len(out)))
 
 
+ROUNDING = {"nearest": 0, "stochastic": 1}
+
+
+def default_rounding(storage: str) -> str:
+    """Stochastic rounding for the 16-bit formats (unbiased: slow changes are
+    not rounded away step after step), nearest otherwise."""
+    return "stochastic" if storage in ("f16s", "bf16s") else "nearest"
+
+
 def make_params(ncomp=2, c_ns=1, tau=(1.0, 1.0), G=0.0, G_ads=(0.0, 0.0), F_ext=(0.0, 0.0, 0.0),
                 g_scale=1.0, storage="f64", rho_shift=(0.0, 0.0), store_scale_log2=0,
-                reservoirs: Sequence = (), check_every=0) -> Params:
+                reservoirs: Sequence = (), check_every=0, rounding=None) -> Params:
     p = Params()
     p.ncomp, p.c_ns = ncomp, c_ns
     t = list(tau) + [1.0] * (2 - len(tau))
@@ -134,6 +144,7 @@ def make_params(ncomp=2, c_ns=1, tau=(1.0, 1.0), G=0.0, G_ads=(0.0, 0.0), F_ext=
         rr = list(rho) + [0.0] * (2 - len(rho))
         p.res[k].rho[0], p.res[k].rho[1] = rr[0], rr[1]
     p.check_every = check_every
+    p.rounding = ROUNDING[rounding or default_rounding(storage)]
     return p
 
 
@@ -199,6 +210,9 @@ class Simulation:
     def time(self) -> int:
         return int(self.lib.lbm_time(self.ctx))
 
+    def set_time(self, t: int):
+        _check(self.lib.lbm_set_time(self.ctx, int(t)), "lbm_set_time")
+
     def last_step_ms(self) -> float:
         return float(self.lib.lbm_last_step_ms(self.ctx))
 
@@ -250,13 +264,15 @@ class Simulation:
             pass
 
 
-def from_workload(w, storage="f32", rho_shift=None, store_scale_log2=0, check_every=0, **kw) -> Simulation:
+def from_workload(w, storage="f32", rho_shift=None, store_scale_log2=0, check_every=0, rounding=None,
+                  **kw) -> Simulation:
     """Simulation of an ``inputs.Workload``."""
     if rho_shift is None:
         rho_shift = default_shift(storage, w.ncomp, w.rho)
     p = make_params(ncomp=w.ncomp, c_ns=w.c_ns, tau=w.tau, G=w.G, G_ads=w.G_ads, F_ext=w.F_ext,
                     g_scale=w.g_scale, storage=storage, rho_shift=rho_shift,
-                    store_scale_log2=store_scale_log2, reservoirs=w.reservoirs, check_every=check_every)
+                    store_scale_log2=store_scale_log2, reservoirs=w.reservoirs, check_every=check_every,
+                    rounding=rounding)
     return Simulation(w.shape, w.ns, w.rho, p, **kw)
 
 
@@ -367,11 +383,12 @@ class Server:
             self._keep[t.value] = out
         return t.value
 
-    def submit_workload(self, w, max_steps, conv_tol=0.0, want_rho=False, rho_shift=None):
+    def submit_workload(self, w, max_steps, conv_tol=0.0, want_rho=False, rho_shift=None, rounding=None):
         if rho_shift is None:
             rho_shift = default_shift(self.storage, w.ncomp, w.rho)
         p = make_params(ncomp=w.ncomp, c_ns=w.c_ns, tau=w.tau, G=w.G, G_ads=w.G_ads, F_ext=w.F_ext,
-                        g_scale=w.g_scale, storage=self.storage, rho_shift=rho_shift, reservoirs=w.reservoirs)
+                        g_scale=w.g_scale, storage=self.storage, rho_shift=rho_shift, reservoirs=w.reservoirs,
+                        rounding=rounding)
         return self.submit(w.shape, w.ns, w.rho, p, max_steps, conv_tol, want_rho)
 
     def poll(self, ticket):

@@ -72,6 +72,47 @@ def test_invalid_parameters_rejected_before_any_device_work(lib, bad):
     assert not ctx.value
 
 
+def test_invalid_rounding_mode_rejected(lib):
+    p = lbm.make_params(ncomp=2, c_ns=1, storage="f16s")
+    p.rounding = 2
+    d, s = lbm.Domain(8, 8, 8), lbm.Sizes()
+    assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_EINVAL
+
+
+_STRUCTS = ["lbm_domain", "lbm_reservoir", "lbm_params", "lbm_sizes", "lbm_device_buffers", "lbm_totals",
+            "lbm_server_cfg", "lbm_request", "lbm_result", "lbm_server_stats"]
+
+
+def _ctypes_of(name):
+    return {"lbm_domain": lbm.Domain, "lbm_reservoir": lbm.Reservoir, "lbm_params": lbm.Params,
+            "lbm_sizes": lbm.Sizes, "lbm_device_buffers": lbm.DeviceBuffers, "lbm_totals": lbm.Totals,
+            "lbm_server_cfg": lbm.ServerCfg, "lbm_request": lbm.Request, "lbm_result": lbm.Result,
+            "lbm_server_stats": lbm.ServerStats}[name]
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every struct of include/lbm.h has, as compiled by the host C compiler,
+    the size and field offsets of its ctypes mirror in the binding."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', 'int main(void) {']
+    for st in _STRUCTS:
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for fname, _ in _ctypes_of(st)._fields_:
+            lines.append(f'printf("{st} {fname} %zu\\n", offsetof({st}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in _STRUCTS:
+        cls = _ctypes_of(st)
+        assert got[(st, "size")] == C.sizeof(cls), st
+        for fname, _ in cls._fields_:
+            assert got[(st, fname)] == getattr(cls, fname).offset, (st, fname)
+
+
 @pytest.mark.parametrize("shape", [(0, 4, 4), (4, -1, 4), (2048, 2048, 1024)])
 def test_bad_domains_rejected(lib, shape):
     p = lbm.make_params()

@@ -85,6 +85,36 @@ def test_single_component_gray_channel_fp64():
     _assert_fields(fo, mo, fg, mg, 1e-10, 1)
 
 
+@pytest.mark.parametrize("ns_slab", [0.05, 0.8])
+def test_gray_channel_reduced_precision(ns_slab):
+    """Brinkman channel of the single-phase benchmark (64 x 64 x 128, walls at
+    y = 0, 63, gray slab 24 <= y < 40, F = 1e-6 along z, tau = 0.8), 20000
+    steps: the velocity field and the channel permeability
+    k = nu <rho u_z> / F (Eq. Permeability) in each storage format against
+    the FP64 path (pinned to the oracle on smaller channels).  Shifted FP32
+    meets the 1e-4 field bar; the 16-bit formats with stochastic rounding meet
+    the 1 % permeability bar with a wide margin (with rounding to nearest the
+    per-step change of this slow flow is rounded away: k would come out 5 %
+    (FP16) and 40 % (BF16) low)."""
+    w = inputs.gray_channel(ns_slab=ns_slab)
+    nu = (0.8 - 0.5) / 3
+
+    def run(storage):
+        sim = lbm.from_workload(w, storage=storage)
+        sim.step(20000)
+        m = sim.moments()
+        sim.close()
+        return nu * (m["rho"][0] * m["u"][2])[:, 1:-1, :].mean() / 1e-6, m["u"][2]
+
+    k0, u0 = run("f64")
+    assert 30 < k0 < 40
+    for storage, tu, tk in (("f32", 1e-4, 1e-5), ("f16s", 5e-3, 1e-3), ("bf16s", 2e-2, 1e-3)):
+        k, u = run(storage)
+        eu = float(np.abs(u - u0).max() / np.abs(u0).max())
+        print(storage, ns_slab, "k", k, k0, "u", eu)
+        assert abs(k / k0 - 1) < tk and eu < tu, (storage, k, k0, eu)
+
+
 def test_droplet_fp32_fields():
     """Density and velocity fields of the 32^3 droplet after 200 steps, FP32."""
     w = inputs.droplet()
@@ -97,18 +127,20 @@ def test_droplet_fp32_fields():
 _U = {"f32": 2.0 ** -24, "f16s": 2.0 ** -11, "bf16s": 2.0 ** -8}
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
-def test_one_step_error_is_the_storage_rounding(storage):
+@pytest.mark.parametrize("storage,rounding", [("f32", "nearest"), ("f16s", "nearest"), ("bf16s", "nearest"),
+                                              ("f16s", "stochastic"), ("bf16s", "stochastic")])
+def test_one_step_error_is_the_storage_rounding(storage, rounding):
     """From a state held exactly in the storage format, one GPU step differs
     from the FP64 oracle's step of the same state by the rounding of the stored
-    result (half a unit in the last place of the shifted value) plus FP32
-    arithmetic: |f_gpu - f_ref| <= u |h_ref| + 2e-6 max|f| (u: unit roundoff)."""
+    result plus FP32 arithmetic: |f_gpu - f_ref| <= k u |h_ref| + 2e-6 max|f|
+    with u the unit roundoff, k = 1 for rounding to nearest (half a unit in the
+    last place) and k = 2 for stochastic rounding (less than one unit)."""
     import oracle
     _, w19, _ = oracle.lattice(19)
     w = inputs.droplet(n=24, radius=6)
     o = oracle_for(w)
     f0 = o.run(o.init(w.rho), 30)
-    sim = lbm.from_workload(w, storage=storage)
+    sim = lbm.from_workload(w, storage=storage, rounding=rounding)
     sim.set_populations(f0)
     fq = sim.populations()          # exactly the stored state, as FP64
     sim.step(1)
@@ -117,7 +149,8 @@ def test_one_step_error_is_the_storage_rounding(storage):
     sim.close()
     fr = o.step(fq)
     h_ref = fr - w19[None, :, None, None, None] * rho0[:, None, None, None, None]
-    bound = _U[storage] * np.abs(h_ref) + 2e-6 * np.abs(fr).max()
+    k = 1.0 if rounding == "nearest" else 2.0
+    bound = k * _U[storage] * np.abs(h_ref) + 2e-6 * np.abs(fr).max()
     excess = np.abs(fg - fr) - bound
     assert excess.max() <= 0.0, (storage, float(excess.max()), float(np.abs(fg - fr).max()))
 
@@ -135,18 +168,20 @@ def _droplet_observables(m, n):
     return R, dp
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-3), ("f16s", 0.05), ("bf16s", 0.25)])
-def test_droplet_observables_reduced_precision(storage, tol):
+@pytest.mark.parametrize("storage,rounding,tol", [("f32", "nearest", 1e-4), ("f16s", "stochastic", 1e-3),
+                                                  ("bf16s", "stochastic", 1e-2)])
+def test_droplet_observables_reduced_precision(storage, rounding, tol):
     """Droplet radius, pressure jump and component masses after 1000 steps in a
     reduced storage format against the FP64 path (itself pinned to the oracle
     by test_droplet_fp64_full_run).  The bounds are the stated accuracy of
-    each format on this workload."""
+    each format on this workload (all within the 1 % bar on the interfacial
+    tension gamma = dp R / 2)."""
     w = inputs.droplet()
     ref = lbm.from_workload(w, storage="f64")
     ref.step(1000)
     mr = ref.moments()
     ref.close()
-    sim = lbm.from_workload(w, storage=storage)
+    sim = lbm.from_workload(w, storage=storage, rounding=rounding)
     sim.step(1000)
     mg = sim.moments()
     sim.close()
@@ -157,6 +192,7 @@ def test_droplet_observables_reduced_precision(storage, tol):
     print(storage, "R", R0, R1, "dp", dp0, dp1, err)
     assert dp0 > 0 and 6 < R0 < 10
     assert max(err.values()) < tol, err
+    assert abs(dp1 * R1 / (dp0 * R0) - 1) < 0.01
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
@@ -175,7 +211,7 @@ def test_full_bounce_back_period_two_bitwise(storage):
     assert not np.array_equal(f3, f0)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
 def test_mass_conserved_on_device(storage):
     w = inputs.random_state((40, 33, 21), 9, ns_choices=[0.0, 0.3, 1.0], rho_range=(0.3, 0.7))
     w.G, w.G_ads, w.F_ext = 0.6, (0.2, -0.2), (1e-4, 0, 0)
@@ -184,7 +220,7 @@ def test_mass_conserved_on_device(storage):
     sim.step(100)
     m1 = sim.totals()["mass"]
     sim.close()
-    tol = {"f64": 1e-12, "f32": 1e-5, "f16s": 1e-2}[storage]
+    tol = {"f64": 1e-12, "f32": 1e-5, "f16s": 1e-3, "bf16s": 1e-2}[storage]
     assert np.allclose(m1, m0, rtol=tol), (m0, m1)
 
 
@@ -228,7 +264,7 @@ def test_tile_width_does_not_change_16bit_results(monkeypatch, storage, shape):
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
 def test_checkpoint_restart_is_bitwise(storage):
     w = inputs.droplet(n=24, radius=6)
     a = lbm.from_workload(w, storage=storage)
@@ -238,6 +274,7 @@ def test_checkpoint_restart_is_bitwise(storage):
     ref = a.populations()
     b = lbm.from_workload(w, storage=storage)
     b.set_populations(f)
+    b.set_time(20)  # stochastic rounding draws on the time step
     b.step(20)
     got = b.populations()
     a.close()
