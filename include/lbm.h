@@ -162,6 +162,42 @@ int lbm_moments(lbm_ctx* ctx, double* rho, double* u, double* p, lbm_totals* tot
 /* FP64 totals only (no per-cell copy-back).  Synchronises. */
 int lbm_totals_get(lbm_ctx* ctx, lbm_totals* tot);
 
+/* Electrolyte-filling diagnostics of Sec. 4, on slabs lo <= coordinate[axis]
+ * < hi of the current (pre-collision) state at time t:
+ *   capillary pressure, Eq. (CapPressure): dp = <p>_inlet - <p>_outlet, the
+ *     means of the pressure of Eq. (SC_pressure) over the inlet and outlet
+ *     slabs (typically the two reservoirs);
+ *   saturation, Eq. (Saturation), of component comp over the pore slab (the
+ *     cells between the membranes):
+ *     S = sum (1 - n_s) [rho_comp >= threshold] / sum (1 - n_s),
+ *     so resolved pore cells (n_s = 0) count once, homogenized cells with
+ *     their fluid fraction 1 - n_s and solid cells (n_s = 1) not at all; n_s
+ *     is component comp's own field when c_ns = 2.  The paper's threshold is
+ *     0.5 mu/lu^3.
+ * FP64, deterministic (fixed-order reduction).  Synchronises.  LBM_EINVAL for
+ * an axis outside 0..2, comp >= ncomp, an empty or out-of-range inlet or
+ * outlet slab, or a pore slab outside the domain.  S is 0 when the pore slab
+ * holds no fluid volume. */
+typedef struct {
+    int32_t axis;                 /* 0: x, 1: y, 2: z                       */
+    int32_t inlet_lo, inlet_hi;
+    int32_t outlet_lo, outlet_hi;
+    int32_t pore_lo, pore_hi;
+    int32_t comp;                 /* component whose saturation is reported */
+    double threshold;             /* density threshold of Eq. (Saturation)  */
+} lbm_fill_query;
+
+typedef struct {
+    double dp;           /* <p>_inlet - <p>_outlet             */
+    double p_inlet;
+    double p_outlet;
+    double saturation;   /* S of component comp                */
+    double pore_volume;  /* sum of (1 - n_s) over the pore slab */
+    int64_t time;
+} lbm_fill_state;
+
+int lbm_fill_state_get(lbm_ctx* ctx, const lbm_fill_query* q, lbm_fill_state* out);
+
 /* Canonical populations (see above) of the current state into f [ncomp*19*N].
  * Reservoir cells hold their prescribed equilibrium.  Synchronises. */
 int lbm_get_populations(lbm_ctx* ctx, double* f);

@@ -27,8 +27,8 @@ inline ScratchLayout scratch_layout(int64_t N, int ncomp)
     s.rho = off; off = align_up(off + sizeof(double) * static_cast<size_t>(ncomp) * N);
     s.u = off; off = align_up(off + sizeof(double) * 3 * static_cast<size_t>(N));
     s.p = off; off = align_up(off + sizeof(double) * static_cast<size_t>(N));
-    s.partials = off; off = align_up(off + sizeof(double) * 5 * hm::moments_max_blocks());
-    s.totals = off; off = align_up(off + sizeof(double) * 5);
+    s.partials = off; off = align_up(off + sizeof(double) * 6 * hm::moments_max_blocks());
+    s.totals = off; off = align_up(off + sizeof(double) * 6);
     s.bytes = off;
     return s;
 }

@@ -76,6 +76,21 @@ hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipSt
 
 int moments_max_blocks();
 
+// Slabs of the filling diagnostics (Sec. 4), coordinates along axis.
+struct FillQuery {
+    int axis;
+    int inlet_lo, inlet_hi, outlet_lo, outlet_hi, pore_lo, pore_hi;
+    int comp;
+    double threshold;
+};
+
+// Eq. (CapPressure) and Eq. (Saturation) sums from the FP64 densities rho and
+// pressure pr: out[6] = {sum p inlet, cells inlet, sum p outlet, cells outlet,
+// sum (1-n_s)[rho_comp >= threshold] pore, sum (1-n_s) pore}.  partials needs
+// 6 * moments_max_blocks() doubles.
+hipError_t launch_fill(const Problem& p, const FillQuery& q, const double* rho, const double* pr, const float* ns,
+                       double* partials, double* out, hipStream_t st);
+
 // One domain of a batched launch (host description).
 struct BatchDomain {
     Problem prob;

@@ -909,21 +909,62 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(Args<typename ST::T> a,
     if (threadIdx.x < 5) partials[blockIdx.x * 5 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partials, int nblocks,
-                                                        double* __restrict__ out)
+// Electrolyte-filling diagnostics (Sec. 4) from the FP64 fields: per-block
+// sums of p and cell counts over the inlet and outlet slabs (Eq. CapPressure),
+// and of (1 - n_s) [rho_comp >= threshold] and (1 - n_s) over the pore slab
+// (Eq. Saturation).
+__global__ __launch_bounds__(kRedThreads) void k_fill(int nx, int ny, int nz, int N, FillQuery q, int ns_field,
+                                                      const double* __restrict__ rho, const double* __restrict__ p,
+                                                      const float* __restrict__ ns, double* __restrict__ partials)
 {
-    __shared__ double red[5][kRedThreads];
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += kRedThreads)
-        for (int k = 0; k < 5; ++k) acc[k] += partials[b * 5 + k];
-    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
+    __shared__ double red[6][kRedThreads];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
+        const int x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+        const int c = q.axis == 0 ? x : (q.axis == 1 ? y : z);
+        if (c >= q.inlet_lo && c < q.inlet_hi) {
+            acc[0] += p[n];
+            acc[1] += 1.0;
+        }
+        if (c >= q.outlet_lo && c < q.outlet_hi) {
+            acc[2] += p[n];
+            acc[3] += 1.0;
+        }
+        if (c >= q.pore_lo && c < q.pore_hi) {
+            const double wfl = 1.0 - static_cast<double>(ns[static_cast<size_t>(ns_field) * N + n]);
+            acc[4] += rho[static_cast<size_t>(q.comp) * N + n] >= q.threshold ? wfl : 0.0;
+            acc[5] += wfl;
+        }
+    }
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int w = kRedThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w)
-            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+            for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 6) partials[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Fixed-order sum of nblocks partials of K doubles each (one block): the
+// result does not depend on timing.
+template <int K>
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partials, int nblocks,
+                                                        double* __restrict__ out)
+{
+    __shared__ double red[K][kRedThreads];
+    double acc[K];
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kRedThreads)
+        for (int k = 0; k < K; ++k) acc[k] += partials[b * K + k];
+    for (int k = 0; k < K; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < K) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1075,7 +1116,18 @@ hipError_t launch_moments(const Problem& p, const void* A, const float* ns, cons
 
 hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, st, partials, nblocks, out);
+    hipLaunchKernelGGL(k_reduce<5>, dim3(1), dim3(kRedThreads), 0, st, partials, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(const Problem& p, const FillQuery& q, const double* rho, const double* pr, const float* ns,
+                       double* partials, double* out, hipStream_t st)
+{
+    const int nb = static_cast<int>(std::min<int64_t>(moments_max_blocks(), (p.N + kRedThreads - 1) / kRedThreads));
+    const int ns_field = p.c_ns == 2 ? q.comp : 0;
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kRedThreads), 0, st, p.nx, p.ny, p.nz, static_cast<int>(p.N), q,
+                       ns_field, rho, pr, ns, partials);
+    hipLaunchKernelGGL(k_reduce<6>, dim3(1), dim3(kRedThreads), 0, st, partials, nb, out);
     return hipGetLastError();
 }
 

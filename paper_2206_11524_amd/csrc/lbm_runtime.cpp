@@ -371,6 +371,35 @@ int lbm_set_reservoir(lbm_ctx* c, int32_t r, const double rho[2])
     return LBM_OK;
 }
 
+int lbm_fill_state_get(lbm_ctx* c, const lbm_fill_query* q, lbm_fill_state* out)
+{
+    if (!c || !q || !out) return LBM_EINVAL;
+    if (q->axis < 0 || q->axis > 2 || q->comp < 0 || q->comp >= c->prm.ncomp) return LBM_EINVAL;
+    const int len = q->axis == 0 ? c->dom.nx : (q->axis == 1 ? c->dom.ny : c->dom.nz);
+    auto slab_ok = [&](int lo, int hi, bool nonempty) { return lo >= 0 && hi <= len && (nonempty ? lo < hi : lo <= hi); };
+    if (!slab_ok(q->inlet_lo, q->inlet_hi, true) || !slab_ok(q->outlet_lo, q->outlet_hi, true) ||
+        !slab_ok(q->pore_lo, q->pore_hi, false) || !std::isfinite(q->threshold))
+        return LBM_EINVAL;
+    const int rc = compute_totals(c, true, nullptr);  // FP64 densities and pressure into the scratch
+    if (rc) return rc;
+    hm::FillQuery f{q->axis, q->inlet_lo, q->inlet_hi, q->outlet_lo, q->outlet_hi, q->pore_lo, q->pore_hi, q->comp,
+                    q->threshold};
+    double* part = reinterpret_cast<double*>(c->scratch + c->sl.partials);
+    double* tots = reinterpret_cast<double*>(c->scratch + c->sl.totals);
+    HIP_TRY(hm::launch_fill(c->prob, f, reinterpret_cast<const double*>(c->scratch + c->sl.rho),
+                            reinterpret_cast<const double*>(c->scratch + c->sl.p), c->ns, part, tots, c->stream));
+    double h[6];
+    HIP_TRY(hipMemcpyAsync(h, tots, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out->p_inlet = h[0] / h[1];
+    out->p_outlet = h[2] / h[3];
+    out->dp = out->p_inlet - out->p_outlet;
+    out->saturation = h[5] > 0.0 ? h[4] / h[5] : 0.0;
+    out->pore_volume = h[5];
+    out->time = c->t;
+    return LBM_OK;
+}
+
 int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
 
 int lbm_set_time(lbm_ctx* c, int64_t t)

@@ -186,6 +186,42 @@ def electrode(n=256, seed=2000, res_layers=16, solid_fraction=0.5, rmin=6.0, rma
                     reservoirs=res, name=f"electrode{n}")
 
 
+def filling_cell(nxy=48, nz=64, seed=2100, res_layers=4, membrane=2, solid_fraction=0.45, rmin=4.0, rmax=7.0,
+                 binder_frac=0.2, G=0.9, G_ads=(-0.04, 0.04), rho_main=1.0, rho_dis=0.03, tau=1.0) -> Workload:
+    """Electrolyte-filling set-up of Sec. 4 along z, two bounce-back fields
+    (c_ns = 2): reservoirs of ``res_layers`` at both ends (electrolyte, index
+    0, at the inlet; gas, index 1, at the outlet), then a semi-permeable
+    membrane of ``membrane`` layers on each side (the inlet one blocks the gas,
+    n_s,gas = 1; the outlet one blocks the electrolyte), and between them a
+    sphere packing (n_s = 1 for both) with a gray binder (same n_s for both)
+    initially filled with gas.  The default G_ads is weakly wetting for the
+    electrolyte (cos theta ~ 0.2 by Eq. contactAngle with G = 0.9)."""
+    g = rng(seed)
+    shape = (nxy, nxy, nz)
+    z0, z1 = res_layers + membrane, nz - res_layers - membrane
+    solid = _sphere_pack(shape, g, solid_fraction, rmin, rmax, z0, z1)
+    noise = _gaussian_smooth(g.standard_normal((nz, nxy, nxy)), 2.0)
+    pore = ~solid
+    pore[:z0] = False
+    pore[z1:] = False
+    vals = noise[pore]
+    thr = np.quantile(vals, 1.0 - binder_frac)
+    binder = pore & (noise >= thr)
+    zscore = (noise - vals.mean()) / vals.std()
+    ns = np.zeros((2, nz, nxy, nxy), np.float32)
+    for c in range(2):
+        ns[c][binder] = np.clip(0.5 + 0.15 * zscore[binder], 0.2, 0.8)
+        ns[c][solid] = 1.0
+    ns[1, res_layers:z0] = 1.0   # inlet membrane: electrolyte only
+    ns[0, z1:nz - res_layers] = 1.0  # outlet membrane: gas only
+    r = np.empty((2, nz, nxy, nxy))
+    r[0], r[1] = rho_dis, rho_main
+    r[0, :z0], r[1, :z0] = rho_main, rho_dis
+    res = [(2, 0, res_layers, (rho_main, rho_dis)), (2, nz - res_layers, nz, (rho_dis, rho_main))]
+    return Workload(shape, ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads), g_scale=3.0,
+                    reservoirs=res, name=f"filling{nxy}x{nz}")
+
+
 def porous_domain(edge, seed, porosity=None, ns_max=0.9, G=0.9, G_ads=(0.1, -0.1),
                   force=1e-5, rho_main=1.0, rho_dis=0.03, tau=1.0) -> Workload:
     """Cubic random-sphere packing (porosity U[0.35, 0.65] unless given) with a

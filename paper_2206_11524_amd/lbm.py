@@ -53,6 +53,17 @@ class DeviceBuffers(C.Structure):
     _fields_ = [("f_a", C.c_void_p), ("f_b", C.c_void_p), ("n_s", C.c_void_p), ("scratch", C.c_void_p)]
 
 
+class FillQuery(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("inlet_lo", C.c_int32), ("inlet_hi", C.c_int32),
+                ("outlet_lo", C.c_int32), ("outlet_hi", C.c_int32), ("pore_lo", C.c_int32),
+                ("pore_hi", C.c_int32), ("comp", C.c_int32), ("threshold", C.c_double)]
+
+
+class FillState(C.Structure):
+    _fields_ = [("dp", C.c_double), ("p_inlet", C.c_double), ("p_outlet", C.c_double),
+                ("saturation", C.c_double), ("pore_volume", C.c_double), ("time", C.c_int64)]
+
+
 class Totals(C.Structure):
     _fields_ = [("mass", C.c_double * 2), ("momentum", C.c_double * 3), ("time", C.c_int64),
                 ("finite", C.c_int32), ("pad", C.c_int32)]
@@ -68,6 +79,7 @@ SIGNATURES = {
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Totals)]),
     "lbm_totals_get": (C.c_int, [C.c_void_p, C.POINTER(Totals)]),
+    "lbm_fill_state_get": (C.c_int, [C.c_void_p, C.POINTER(FillQuery), C.POINTER(FillState)]),
     "lbm_get_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_set_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_set_reservoir": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
@@ -234,6 +246,15 @@ class Simulation:
 
     def totals(self):
         return self.moments(fields=False)
+
+    def fill_state(self, axis, inlet, outlet, pore, comp=0, threshold=0.5):
+        """Capillary pressure (Eq. CapPressure) and saturation (Eq. Saturation)
+        on slabs given as (lo, hi) coordinate ranges along ``axis``."""
+        q = FillQuery(axis, inlet[0], inlet[1], outlet[0], outlet[1], pore[0], pore[1], comp, threshold)
+        out = FillState()
+        _check(self.lib.lbm_fill_state_get(self.ctx, C.byref(q), C.byref(out)), "lbm_fill_state_get")
+        return {"dp": out.dp, "p_inlet": out.p_inlet, "p_outlet": out.p_outlet, "saturation": out.saturation,
+                "pore_volume": out.pore_volume, "time": out.time}
 
     def populations(self) -> np.ndarray:
         nx, ny, nz = self.shape

@@ -80,12 +80,13 @@ def test_invalid_rounding_mode_rejected(lib):
 
 
 _STRUCTS = ["lbm_domain", "lbm_reservoir", "lbm_params", "lbm_sizes", "lbm_device_buffers", "lbm_totals",
-            "lbm_server_cfg", "lbm_request", "lbm_result", "lbm_server_stats"]
+            "lbm_fill_query", "lbm_fill_state", "lbm_server_cfg", "lbm_request", "lbm_result", "lbm_server_stats"]
 
 
 def _ctypes_of(name):
     return {"lbm_domain": lbm.Domain, "lbm_reservoir": lbm.Reservoir, "lbm_params": lbm.Params,
             "lbm_sizes": lbm.Sizes, "lbm_device_buffers": lbm.DeviceBuffers, "lbm_totals": lbm.Totals,
+            "lbm_fill_query": lbm.FillQuery, "lbm_fill_state": lbm.FillState,
             "lbm_server_cfg": lbm.ServerCfg, "lbm_request": lbm.Request, "lbm_result": lbm.Result,
             "lbm_server_stats": lbm.ServerStats}[name]
 
@@ -144,6 +145,11 @@ def test_misaligned_caller_buffers_rejected(lib):
     ctx = C.c_void_p()
     assert lib.lbm_create(C.byref(d), ns.ctypes.data, rho.ctypes.data, C.byref(p), C.byref(bufs), None,
                           C.byref(ctx)) == lbm.LBM_EINVAL
+
+
+def test_fill_query_rejected_without_context(lib):
+    q, out = lbm.FillQuery(2, 0, 4, 60, 64, 4, 60, 0, 0.5), lbm.FillState()
+    assert lib.lbm_fill_state_get(None, C.byref(q), C.byref(out)) == lbm.LBM_EINVAL
 
 
 def test_null_context_calls_are_rejected(lib):

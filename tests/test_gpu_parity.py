@@ -305,3 +305,25 @@ def test_reservoir_density_change():
     fg = sim.populations()
     sim.close()
     assert rel_max_err(fg, fo) < 1e-10
+
+
+def test_fill_state_matches_definitions_on_oracle_fields():
+    """Capillary pressure (Eq. CapPressure) and saturation (Eq. Saturation) of
+    the filling set-up with membranes (two n_s fields), FP64, after 40 steps:
+    the GPU reduction against the definitions applied to the oracle's fields."""
+    w = inputs.filling_cell(nxy=20, nz=28, rmin=2.0, rmax=4.0)
+    nz = w.shape[2]
+    o = oracle_for(w)
+    mo = o.moments(o.run(o.init(w.rho), 40))
+    sim = lbm.from_workload(w, storage="f64")
+    sim.step(40)
+    for comp, thr in ((0, 0.5), (1, 0.5), (0, 0.1)):
+        st = sim.fill_state(2, (0, 4), (nz - 4, nz), (6, nz - 6), comp=comp, threshold=thr)
+        p = mo["p"]
+        dp = p[:4].mean() - p[nz - 4:].mean()
+        wfl = 1.0 - w.ns[comp][6:nz - 6].astype(np.float64)
+        sat = (wfl * (mo["rho"][comp][6:nz - 6] >= thr)).sum() / wfl.sum()
+        assert abs(st["dp"] - dp) <= 1e-10 * abs(p).max(), (st["dp"], dp)
+        assert abs(st["saturation"] - sat) < 1e-12 and abs(st["pore_volume"] / wfl.sum() - 1) < 1e-12
+        assert st["time"] == 40
+    sim.close()
