@@ -51,6 +51,7 @@ class BatchRunner {
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         const int threads = ncomp * tile_x * tile_y;
         grid_ = std::max(8, cus * (threads >= 1024 ? 2 : 4));
+        cus_ = std::max(cus, 1);
         for (int j = 0; j < 2; ++j) {
             if (hipMalloc(&dev_[j], bytes_) != hipSuccess) return LBM_ENOMEM;
             if (hipHostMalloc(reinterpret_cast<void**>(&host_[j]), bytes_, hipHostMallocDefault) != hipSuccess)
@@ -93,7 +94,20 @@ class BatchRunner {
         const int j = slot_;
         slot_ ^= 1;
         HIP_TRY(hipEventSynchronize(copied_[j]));  // host copy j is free again
-        hm::batch_encode(storage_, d, n, tx_, ty_, host_[j]);
+        // z-chunks from the batch as a whole: about four tiles per CU, no
+        // tile longer than 32 planes (blocks stride over tiles of unequal
+        // domains, short tiles balance them), none shorter than 16 (each
+        // chunk re-reads two halo planes)
+        balanced_.assign(d, d + n);
+        int64_t cols = 0;
+        for (const hm::BatchDomain& b : balanced_)
+            cols += static_cast<int64_t>((b.prob.nx + tx_ - 1) / tx_) * ((b.prob.ny + ty_ - 1) / ty_);
+        const int64_t per_cols = std::max<int64_t>(1, (4 * static_cast<int64_t>(cus_) + cols - 1) / std::max<int64_t>(cols, 1));
+        for (hm::BatchDomain& b : balanced_) {
+            const int64_t chunks = std::max<int64_t>(per_cols, (b.prob.nz + 31) / 32);
+            b.zchunk = static_cast<int>(std::min<int64_t>(b.prob.nz, std::max<int64_t>(16, (b.prob.nz + chunks - 1) / chunks)));
+        }
+        hm::batch_encode(storage_, balanced_.data(), n, tx_, ty_, host_[j]);
         HIP_TRY(hipMemcpyAsync(dev_[j], host_[j], bytes_, hipMemcpyHostToDevice, stream_));
         HIP_TRY(hipEventRecord(copied_[j], stream_));
         HIP_TRY(hipEventRecord(t0_, stream_));
@@ -139,7 +153,8 @@ class BatchRunner {
     }
 
   private:
-    int storage_ = 0, ncomp_ = 0, c_ns_ = 0, tx_ = 64, ty_ = 8, kmax_ = 1, grid_ = 512;
+    int storage_ = 0, ncomp_ = 0, c_ns_ = 0, tx_ = 64, ty_ = 8, kmax_ = 1, grid_ = 512, cus_ = 256;
+    std::vector<hm::BatchDomain> balanced_;
     size_t bytes_ = 0;
     hipStream_t stream_ = nullptr;
     void* dev_[2] = {nullptr, nullptr};
@@ -156,8 +171,7 @@ hm::BatchDomain domain_of(const lbm_ctx* c, int steps)
 {
     hm::BatchDomain d{};
     d.prob = c->prob;
-    // many domains share the GPU, so chunks stay long (few halo planes)
-    d.zchunk = std::min(c->prob.nz, std::max(32, c->launch.zchunk));
+    d.zchunk = c->prob.nz;  // set per launch by BatchRunner::run
     d.buf[0] = c->buf[0];
     d.buf[1] = c->buf[1];
     d.ns = c->ns;
