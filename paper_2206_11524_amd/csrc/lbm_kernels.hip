@@ -496,7 +496,12 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     const int TYe = min(TY, a.ny - y0);
     const int plane = a.nx * a.ny;
 
-    const int s = NC == 1 ? 0 : static_cast<int>(threadIdx.x) / NTC;  // component of this thread
+    // component of this thread; NTC is a multiple of 64, so it is the same
+    // for every lane of a wave: saying so keeps the buffer descriptors and
+    // everything derived from s in scalar registers (otherwise each load
+    // becomes a loop over the distinct descriptor values of the wave)
+    const int s = NC == 1 ? 0 : __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / NTC);
+    static_assert(NTC % 64 == 0, "a wave must not straddle two components");
     const int tl = static_cast<int>(threadIdx.x) - s * NTC;
     const int lx = tl % TX;
     const int ly = tl / TX;
@@ -557,20 +562,26 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                                 static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};  // c_z = +1
         pull<ST, T>(ra, dir_bytes, so, q, a.inv_scale, h);
     };
+    // A select per value rather than a branch: in divergent control flow a
+    // branch makes the compiler merge the two versions of all 19 values
+    // through copies, doubling the registers they hold.
     auto reservoir_override = [&](int res, T h[kQ]) {
-        if (res >= 0) {
-            const T dr = a.res_dr[res][s];
+        const bool in = res >= 0;
+        const T dr = a.res_dr[in ? res : 0][s];
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) h[i] = wgt<T>(i) * dr;
-        }
+        for (int i = 0; i < kQ; ++i) h[i] = in ? wgt<T>(i) * dr : h[i];
     };
 
     // Stage plane p into LDS slot `slot`: densities of the own cell and of
     // the ring cell, first moments of the own cell (slot js, none if js < 0),
     // n_s; the own cell's populations stay in h for the collision.
     auto stage_plane = [&](int p, int slot, int js, T h[kQ]) {
+        // issue the own and the ring loads before either is consumed, so a
+        // ring lane waits for one memory round trip per plane, not two
+        T hr[kQ];
+        if (act) pull_plane(p, qme, h);
+        if (ring) pull_plane(p, qring, hr);
         if (act) {
-            pull_plane(p, qme, h);
             reservoir_override(reservoir_of(a, x, y, p), h);
             s_rho[slot][s][me] = a.rho0[s] + sum19(h);
             if (NC == 2 && js >= 0) {
@@ -580,8 +591,6 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
             }
         }
         if (ring) {
-            T hr[kQ];
-            pull_plane(p, qring, hr);
             reservoir_override(reservoir_of(a, rx, ry, p), hr);
             s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
         }
