@@ -20,18 +20,26 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hmcsc_oracle.c")
 LIB = os.path.join(HERE, "libhmcsc_oracle.so")
+# A compiled copy elsewhere (the tests' mutation check loads deliberately
+# broken copies this way); never rebuilt here.
+LIB_OVERRIDE = os.environ.get("HMCSC_ORACLE_LIB")
 MAX_RES = 4
+CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+          "-Wall", "-Wextra"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
-    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+def compile_to(src: str, out: str, verbose: bool = False) -> str:
+    """Compile an oracle source with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    cmd = ["gcc", *CFLAGS, "-I", HERE, "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    return compile_to(SRC, LIB, verbose)
 
 
 class _Res(C.Structure):
@@ -100,9 +108,12 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        lib = C.CDLL(LIB)
+        if LIB_OVERRIDE:
+            lib = C.CDLL(LIB_OVERRIDE)
+        else:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build()
+            lib = C.CDLL(LIB)
         dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
         pp = C.POINTER(_Params)
         lib.href_lattice.argtypes = [C.c_int32, C.POINTER(C.c_int32),

@@ -1,0 +1,79 @@
+"""The pins constrain the oracle: deliberately wrong copies of it fail them.
+
+Each mutant is the oracle source with one plausible mistake planted in it
+(a sign, a neighbour taken on the wrong side, a dropped factor, a wrong
+opposite direction, ...).  It is compiled into a temporary library and the
+fast CPU pins run against it in a subprocess (HMCSC_ORACLE_LIB).  Every mutant
+must make at least one pin fail; the unmodified source must pass the same
+pins.  Nothing here touches the GPU library or the repository's built oracle.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TESTS = os.path.join(ROOT, "tests")
+PINS = ["test_oracle_forces.py", "test_oracle_closed_forms.py", "test_oracle_invariants.py",
+        "test_oracle_lattice.py", "test_oracle_shear_wave.py", "test_oracle_brinkman.py"]
+
+# (name, text in hmcsc_oracle.c, replacement, which occurrence (1-based))
+MUTANTS = [
+    ("cohesion sign", "Finter[a] = -rho_s[s] * p->G * g[a];", "Finter[a] = rho_s[s] * p->G * g[a];", 1),
+    ("adhesion sign", "Fads[a] = -rho_s[s] * p->G_ads[s] * g[a];", "Fads[a] = rho_s[s] * p->G_ads[s] * g[a];", 1),
+    ("cohesion neighbour at x - c_i", "wrap(x + L->c[i][0], p->nx), wrap(y + L->c[i][1], p->ny),",
+     "wrap(x - L->c[i][0], p->nx), wrap(y - L->c[i][1], p->ny),", 1),
+    ("adhesion neighbour at x - c_i", "wrap(x + L->c[i][0], p->nx), wrap(y + L->c[i][1], p->ny),",
+     "wrap(x - L->c[i][0], p->nx), wrap(y - L->c[i][1], p->ny),", 2),
+    ("streaming to x - c_i", "wrap(x + L->c[i][0], p->nx), wrap(y + L->c[i][1], p->ny),",
+     "wrap(x - L->c[i][0], p->nx), wrap(y - L->c[i][1], p->ny),", 3),
+    ("external force not split by density", "rho_s[s] / rho * p->F_ext[a]", "p->F_ext[a]", 1),
+    ("bounce-back without the opposite direction", "nsx * fl[s][L->opp[i]]", "nsx * fl[s][i]", 1),
+    ("relaxation not weighted by 1 - n_s", "- (1.0 - nsx) / p->tau[s] * (fl[s][i] - feq)",
+     "- 1.0 / p->tau[s] * (fl[s][i] - feq)", 1),
+    ("bounce-back blend without 1 - n_s", "post[s][i] = (1.0 - nsx) * fl[s][i]", "post[s][i] = fl[s][i]", 1),
+    ("second-order term of the equilibrium doubled", "(cu * cu) / (2.0 * CS2 * CS2)", "(cu * cu) / (CS2 * CS2)", 1),
+    ("velocity term of the equilibrium halved", "1.0 + cu / CS2", "1.0 + cu / (2.0 * CS2)", 1),
+    ("force shift without tau", "p->tau[s] * Ft[a] / rho_s[s]", "Ft[a] / rho_s[s]", 1),
+    ("common velocity not tau-weighted", "num[a] += j[s][a] / p->tau[s];", "num[a] += j[s][a];", 1),
+    ("macroscopic velocity without the half force", "(js + Ft[s][a] / 2.0)", "(js + Ft[s][a])", 1),
+    ("macroscopic velocity not weighted by 1 - n_s", "m += (1.0 - ns_at(p, ns, s, n)) * (js", "m += (js", 1),
+    ("reservoirs not reset", "    reset_reservoirs(p, L, f_out);\n    return 0;", "    return 0;", 1),
+    ("axis weight 1/16", "w1 = 1.0 / 18.0;", "w1 = 1.0 / 16.0;", 1),
+    ("stencil scale ignored", "g[a] += p->g_scale * L->w[i] * r_nb * L->c[i][a];",
+     "g[a] += L->w[i] * r_nb * L->c[i][a];", 1),
+]
+
+
+def _mutate(src: str, old: str, new: str, k: int) -> str:
+    pos = -1
+    for _ in range(k):
+        pos = src.find(old, pos + 1)
+        assert pos >= 0, f"mutation site not found: {old!r} (occurrence {k})"
+    return src[:pos] + new + src[pos + len(old):]
+
+
+def _run_pins(lib: str) -> subprocess.CompletedProcess:
+    env = dict(os.environ, HMCSC_ORACLE_LIB=lib)
+    cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+           *[os.path.join(TESTS, f) for f in PINS]]
+    return subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def test_unmodified_oracle_passes_the_pins(tmp_path):
+    lib = ref.compile_to(ref.SRC, str(tmp_path / "orig.so"))
+    r = _run_pins(lib)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name,old,new,k", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_fails_a_pin(tmp_path, name, old, new, k):
+    src = open(ref.SRC).read()
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(_mutate(src, old, new, k))
+    lib = ref.compile_to(str(msrc), str(tmp_path / "mutant.so"))
+    r = _run_pins(lib)
+    assert r.returncode != 0, f"no pin caught the mutant '{name}'"
