@@ -235,6 +235,29 @@ __device__ __forceinline__ int reservoir_of(const Args<T>& a, int x, int y, int 
     return r_found;
 }
 
+// The same search for the step kernel, returning the shifted density of
+// component s in that reservoir.  The loop runs over the slots with
+// compile-time indices and s is the same for the whole wave, so every
+// parameter is read with scalar loads (a per-lane indexed load would be a
+// vector memory load, and waiting for it would wait for every load issued
+// before it).
+template <typename T>
+__device__ __forceinline__ bool reservoir_dr(const Args<T>& a, int s, int x, int y, int z, T& dr)
+{
+    bool in = false;
+    dr = T(0);
+#pragma unroll
+    for (int r = 0; r < kMaxRes; ++r) {
+        if (r < a.n_res) {
+            const int c = a.res_axis[r] == 0 ? x : (a.res_axis[r] == 1 ? y : z);
+            const bool hit = !in && c >= a.res_lo[r] && c < a.res_hi[r];
+            dr = hit ? (s == 0 ? a.res_dr[r][0] : a.res_dr[r][1]) : dr;
+            in = in || hit;
+        }
+    }
+    return in;
+}
+
 __device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrap_inc(int v, int n) { return v == n - 1 ? 0 : v + 1; }
 
@@ -304,6 +327,17 @@ __device__ __forceinline__ void pull(rsrc_t r, uint32_t dir_bytes, const uint32_
     for (int i = 0; i < kQ; ++i)
         h[i] = ST::dec(ST::bld(r, q.o[CY[i] + 1][CX[i] + 1], soff[CZ[i] + 1] + static_cast<uint32_t>(i) * dir_bytes),
                        inv_scale);
+}
+
+// The same loads without decoding: the raw values can stay in flight while
+// other work runs, and are decoded where they are consumed.
+template <typename ST>
+__device__ __forceinline__ void pull_raw(rsrc_t r, uint32_t dir_bytes, const uint32_t soff[3], const PlaneOffs& q,
+                                         typename ST::E e[kQ])
+{
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+        e[i] = ST::bld(r, q.o[CY[i] + 1][CX[i] + 1], soff[CZ[i] + 1] + static_cast<uint32_t>(i) * dir_bytes);
 }
 
 template <typename T>
@@ -463,9 +497,16 @@ struct TileShared {
     static constexpr int LW = TX + 2;
     static constexpr int LP = LW * (TY + 2);
     static constexpr int NTC = TX * TY;
+    static constexpr int NT = NC * NTC;
+    // FP32 arithmetic: the populations of the plane staged last wait here
+    // (private to each thread) until it is collided, which frees the
+    // registers that keep the next plane's loads in flight
+    static constexpr size_t kBase = sizeof(T) * (4 * NC * LP + 3 * NC * 3 * NTC) + sizeof(float) * 4 * CNS * LP;
+    static constexpr bool kPipe = sizeof(T) == 4 && kBase + sizeof(T) * kQ * NT <= 160 * 1024;
     T rho[4][NC][LP];
     float ns[4][CNS][LP];
     T j[3][NC][3][NTC];
+    T hs[kPipe ? kQ : 1][kPipe ? NT : 1];
 };
 
 // The sweep of one tile column (logical tile index L of the domain described
@@ -508,7 +549,10 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     const bool act = lx < TXe && ly < TYe;
     const int x = x0 + min(lx, TXe - 1);
     const int y = y0 + min(ly, TYe - 1);
-    const int me = (ly + 1) * LW + (lx + 1);
+    // LDS cell and first-moment slot of the (clamped) own cell: a lane beyond
+    // a ragged tile edge duplicates the last active lane of its row/column
+    const int me = (y - y0 + 1) * LW + (x - x0 + 1);
+    const int tj = (y - y0) * TX + (x - x0);
     const PlaneOffs qme = plane_offs<E>(x, y, a.nx, a.ny);
     const uint32_t own = static_cast<uint32_t>((y * a.nx + x) * static_cast<int>(sizeof(E)));
 
@@ -565,9 +609,9 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     // A select per value rather than a branch: in divergent control flow a
     // branch makes the compiler merge the two versions of all 19 values
     // through copies, doubling the registers they hold.
-    auto reservoir_override = [&](int res, T h[kQ]) {
-        const bool in = res >= 0;
-        const T dr = a.res_dr[in ? res : 0][s];
+    auto reservoir_override = [&](int cx, int cy, int cz, T h[kQ]) {
+        T dr;
+        const bool in = reservoir_dr(a, s, cx, cy, cz, dr);
 #pragma unroll
         for (int i = 0; i < kQ; ++i) h[i] = in ? wgt<T>(i) * dr : h[i];
     };
@@ -582,16 +626,16 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
         if (act) pull_plane(p, qme, h);
         if (ring) pull_plane(p, qring, hr);
         if (act) {
-            reservoir_override(reservoir_of(a, x, y, p), h);
+            reservoir_override(x, y, p, h);
             s_rho[slot][s][me] = a.rho0[s] + sum19(h);
             if (NC == 2 && js >= 0) {
-                s_j[js][s][0][tl] = first_moment<T, 0>(h);
-                s_j[js][s][1][tl] = first_moment<T, 1>(h);
-                s_j[js][s][2][tl] = first_moment<T, 2>(h);
+                s_j[js][s][0][tj] = first_moment<T, 0>(h);
+                s_j[js][s][1][tj] = first_moment<T, 1>(h);
+                s_j[js][s][2][tj] = first_moment<T, 2>(h);
             }
         }
         if (ring) {
-            reservoir_override(reservoir_of(a, rx, ry, p), hr);
+            reservoir_override(rx, ry, p, hr);
             s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
         }
         const float* nsp = ns + static_cast<size_t>(p) * plane;
@@ -604,8 +648,8 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
 
     // Collision of plane z of this thread's component from h (pre-collision,
     // shifted) and the LDS slots of planes z-1, z, z+1.
-    auto collide = [&](int z, int sm, int s0, int sp, int js, const T h[kQ]) {
-        if (!act) return;
+    auto collide = [&](int z, int sm, int s0, int sp, int js, const T h[kQ], bool guard) {
+        if (guard && !act) return;
         T jc[NC][3];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -615,7 +659,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                 jc[c][2] = first_moment<T, 2>(h);
             } else {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) jc[c][d] = s_j[js][c][d][tl];
+                for (int d = 0; d < 3; ++d) jc[c][d] = s_j[js][c][d][tj];
             }
         }
         T ueq[3], rho_own, n;
@@ -650,27 +694,129 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
         }
     };
 
-    T hA[kQ];
-    T hB[kQ];
-
     // plane p (zs-1 <= p <= ze) uses density slot (p - zs + 1) mod 4 and
     // first-moment slot (p - zs) mod 3
     auto rslot = [&](int p) { return (p - zs + 1) & 3; };
     auto jslot = [&](int p) { return (p - zs) % 3; };
 
-    // prologue: plane zs-1 (densities only), plane zs (kept in hA)
-    stage_plane(wrapz(zs - 1), rslot(zs - 1), -1, hB);
-    stage_plane(zs, rslot(zs), jslot(zs), hA);
+    if constexpr (TileShared<ST, NC, CNS, TX, TY>::kPipe) {
+        // Three planes at a time: plane z is collided from registers, plane
+        // z+1 waits in LDS (hs), and the own loads of plane z+2 are in flight
+        // over the barrier and the collision of plane z.
+        //
+        // The compiler counts outstanding memory operations per control-flow
+        // path, and after a branch that may have skipped some it has to wait
+        // as if they had been issued last; a load or store under a per-lane
+        // condition would therefore make every later wait drain the loads
+        // kept in flight.  So nothing here touches memory conditionally:
+        // lanes beyond a ragged tile edge duplicate an active lane (same
+        // cell, same LDS slots, identical values written twice), lanes
+        // without a ring cell load at offsets past the buffer's range
+        // (dropped by the range check), and lanes without an n_s cell
+        // duplicate cell 0 of the staging list.
+        constexpr int NT_ = TileShared<ST, NC, CNS, TX, TY>::NT;
+        constexpr uint32_t kOff = 0x80000000u;  // beyond any buffer of a single component below 2 GiB
+        E rr[kQ];  // own populations of the next plane to stage, raw
+        E er[kQ];  // ring populations of the plane being staged, raw
+        T* hs = &sh.hs[0][0] + threadIdx.x;
+        PlaneOffs qr = qring;
+        if (!ring)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) qr.o[b][c] |= kOff;
+        // list cell 0 is the corner (x0 - 1, y0 - 1), LDS index 0
+        const int ns_off0 = (((y0 - 1) % a.ny + a.ny) % a.ny) * a.nx + ((x0 - 1) % a.nx + a.nx) % a.nx;
+        int nl[NSMAX], no[NSMAX];
+#pragma unroll
+        for (int k = 0; k < NSMAX; ++k) {
+            nl[k] = ns_lds[k] >= 0 ? ns_lds[k] : 0;
+            no[k] = ns_lds[k] >= 0 ? ns_off[k] : ns_off0;
+        }
+        auto issue = [&](int p, const PlaneOffs& q, E e[kQ]) {
+            const uint32_t so[3] = {static_cast<uint32_t>(wrapz(p + 1)) * plane_bytes,
+                                    static_cast<uint32_t>(p) * plane_bytes,
+                                    static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};
+            pull_raw<ST>(ra, dir_bytes, so, q, e);
+        };
+        // Stage plane p, whose own loads are in rr: ring loads and n_s are
+        // issued first; the own values give the density and first moments
+        // and go to hs, whose previous content (the plane before) moves to
+        // hz; then the own loads of plane pn are issued, and only after them
+        // the ring values are consumed, so a wait for the ring does not wait
+        // for plane pn.
+        auto stage_pipe = [&](int p, int slot, int js, int pn, T hz[kQ]) {
+            if constexpr (NC == 2) issue(p, qr, er);
+            const float* nsp = ns + static_cast<size_t>(p) * plane;
+            float nsv[NSMAX][CNS];
+#pragma unroll
+            for (int k = 0; k < NSMAX; ++k)
+#pragma unroll
+                for (int c = 0; c < CNS; ++c) nsv[k][c] = nsp[static_cast<size_t>(c) * a.N + no[k]];
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                T h[kQ];
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) h[i] = ST::dec(rr[i], a.inv_scale);
+                reservoir_override(x, y, p, h);
+                s_rho[slot][s][me] = a.rho0[s] + sum19(h);
+                if (NC == 2 && js >= 0) {
+                    s_j[js][s][0][tj] = first_moment<T, 0>(h);
+                    s_j[js][s][1][tj] = first_moment<T, 1>(h);
+                    s_j[js][s][2][tj] = first_moment<T, 2>(h);
+                }
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    hz[i] = hs[i * NT_];
+                    hs[i * NT_] = h[i];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            issue(pn, qme, rr);
+            __builtin_amdgcn_sched_barrier(0);
+            if (ring) {
+                T hr[kQ];
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) hr[i] = ST::dec(er[i], a.inv_scale);
+                reservoir_override(rx, ry, p, hr);
+                s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
+            }
+#pragma unroll
+            for (int k = 0; k < NSMAX; ++k)
+#pragma unroll
+                for (int c = 0; c < CNS; ++c) s_ns[slot][c][nl[k]] = nsv[k][c];
+        };
 
-    // sweep, two planes per iteration so the register sets alternate roles
-    for (int z = zs; z < ze; z += 2) {
-        stage_plane(wrapz(z + 1), rslot(z + 1), jslot(z + 1), hB);
-        __syncthreads();
-        collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hA);
-        if (z + 1 >= ze) break;
-        stage_plane(wrapz(z + 2), rslot(z + 2), jslot(z + 2), hA);
-        __syncthreads();
-        collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), jslot(z + 1), hB);
+        T hz[kQ];
+        // prologue: plane zs-1 (densities only), plane zs (to hs)
+        issue(wrapz(zs - 1), qme, rr);
+        stage_pipe(wrapz(zs - 1), rslot(zs - 1), -1, zs, hz);
+        stage_pipe(zs, rslot(zs), jslot(zs), wrapz(zs + 1), hz);
+        for (int z = zs; z < ze; ++z) {
+            // after the last plane the next loads repeat the one just staged (L2 hits)
+            const int pn = z + 2 <= ze ? wrapz(z + 2) : wrapz(z + 1);
+            stage_pipe(wrapz(z + 1), rslot(z + 1), jslot(z + 1), pn, hz);
+            __syncthreads();
+            collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hz, false);
+        }
+    } else {
+        T hA[kQ];
+        T hB[kQ];
+
+        // prologue: plane zs-1 (densities only), plane zs (kept in hA)
+        stage_plane(wrapz(zs - 1), rslot(zs - 1), -1, hB);
+        stage_plane(zs, rslot(zs), jslot(zs), hA);
+
+        // sweep, two planes per iteration so the register sets alternate roles
+        for (int z = zs; z < ze; z += 2) {
+            stage_plane(wrapz(z + 1), rslot(z + 1), jslot(z + 1), hB);
+            __syncthreads();
+            collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hA, true);
+            if (z + 1 >= ze) break;
+            stage_plane(wrapz(z + 2), rslot(z + 2), jslot(z + 2), hA);
+            __syncthreads();
+            collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), jslot(z + 1), hB, true);
+        }
     }
 }
 
