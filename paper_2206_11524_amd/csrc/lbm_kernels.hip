@@ -50,6 +50,8 @@ __host__ __device__ constexpr T wgt(int i)
 // after the whole domain has streamed through the caches.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
 constexpr int kNT = 2;  // cache policy: non-temporal
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes)
@@ -109,23 +111,18 @@ struct F16 : Half16 {
     {
         return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v * scale));
     }
-    // Stochastic rounding with 16 random bits r16: the value rounds up with
-    // probability equal to its fraction of the binary16 spacing.  Add 13
-    // random bits below the spacing to the FP32 magnitude and cut them.
-    // Magnitudes below 2^-14 are first lifted by 2^-14 into the binade
-    // [2^-14, 2^-13), whose spacing 2^-24 is that of the binary16 subnormals,
-    // and lowered again afterwards (exact); the lift itself rounds by at most
-    // 2^-13 of a spacing.  Inf and NaN keep their class; beyond the binary16
-    // range the conversion gives inf as rounding to nearest does.
+    // Stochastic rounding with 16 random bits r16 (v_cvt_sr_f16_f32): the
+    // instruction reads its random operand as a binary fraction from the top
+    // bit down and rounds the magnitude up with probability equal to the
+    // value's fraction of the binary16 spacing, subnormals included (checked
+    // on the device: up only for bit 31 at half a spacing, frequencies equal
+    // to the fraction, exact values unchanged, inf and NaN kept).  r16 goes to
+    // the top half, so the probability is resolved to 2^-16.
     static __device__ __forceinline__ E enc_sr(T v, T scale, uint32_t r16)
     {
-        const uint32_t u = __float_as_uint(v * scale);
-        const uint32_t sign = u & 0x80000000u;
-        const float ax = __uint_as_float(u ^ sign);
-        const float lift = ax < 0x1p-14f ? 0x1p-14f : 0.0f;
-        const uint32_t q = (__float_as_uint(ax + lift) + (r16 >> 3)) & ~0x1fffu;
-        const float y = __uint_as_float(q) - lift;
-        return __builtin_bit_cast(uint16_t, static_cast<_Float16>(__uint_as_float(__float_as_uint(y) | sign)));
+        half2_t h = {0, 0};
+        h = __builtin_amdgcn_cvt_sr_f16_f32(h, v * scale, r16 << 16, false);
+        return __builtin_bit_cast(uint16_t, h[0]);
     }
 };
 struct BF16 : Half16 {
@@ -142,14 +139,13 @@ struct BF16 : Half16 {
         u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
         return static_cast<E>(u >> 16);
     }
-    // Stochastic rounding: 16 random bits added below the kept bits before
-    // truncation.
+    // Stochastic rounding with 16 random bits (v_cvt_sr_bf16_f32, the same
+    // convention as the binary16 instruction).
     static __device__ __forceinline__ E enc_sr(T v, T scale, uint32_t r16)
     {
-        uint32_t u = __float_as_uint(v * scale);
-        if ((u & 0x7f800000u) == 0x7f800000u) return enc(v, scale);
-        u += r16;
-        return static_cast<E>(u >> 16);
+        bf162_t h = {0, 0};
+        h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v * scale, r16 << 16, false);
+        return __builtin_bit_cast(uint16_t, h[0]);
     }
 };
 
@@ -382,6 +378,15 @@ __device__ __forceinline__ void stencil(const V* pm, const V* p0, const V* pp, i
     for (int d = 0; d < 3; ++d) g[d] = ax[d] * (T(1) / T(18)) + dg[d] * (T(1) / T(36));
 }
 
+// 1/x: correctly rounded in FP64; in FP32 the hardware reciprocal (within
+// one unit in the last place), one instruction instead of a division
+template <typename T>
+__device__ __forceinline__ T recip(T x)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(x);
+    else return T(1) / x;
+}
+
 // Per-cell physics shared by the step kernels: every kernel evaluates the
 // same expressions, so the result of a cell does not depend on which kernel
 // or launch shape updated it.
@@ -409,8 +414,8 @@ __device__ __forceinline__ void cell_velocity(const Args<T>& a, int s, int me, c
 #pragma unroll
         for (int d = 0; d < 3; ++d) num[d] += jc[c][d] * a.inv_tau[c];
     }
-    const T inv_den = den > T(0) ? T(1) / den : T(0);
-    const T inv_rho = rho > T(0) ? T(1) / rho : T(0);
+    const T inv_den = den > T(0) ? recip(den) : T(0);
+    const T inv_rho = rho > T(0) ? recip(rho) : T(0);
     const int cn = CNS == 2 ? s : 0;
     T ga[3];
     stencil<T, float, LW>(ns_m + cn * LP, ns_0 + cn * LP, ns_p + cn * LP, me, ga);
@@ -606,14 +611,18 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                                 static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};  // c_z = +1
         pull<ST, T>(ra, dir_bytes, so, q, a.inv_scale, h);
     };
-    // A select per value rather than a branch: in divergent control flow a
-    // branch makes the compiler merge the two versions of all 19 values
-    // through copies, doubling the registers they hold.
+    // A select per value rather than a per-lane branch: in divergent control
+    // flow a branch makes the compiler merge the two versions of all 19
+    // values through copies, doubling the registers they hold.  The selects
+    // are skipped as a whole when no lane of the wave is in a reservoir (the
+    // common case; a branch taken by the whole wave).
     auto reservoir_override = [&](int cx, int cy, int cz, T h[kQ]) {
         T dr;
         const bool in = reservoir_dr(a, s, cx, cy, cz, dr);
+        if (__builtin_amdgcn_ballot_w64(in) != 0) {
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) h[i] = in ? wgt<T>(i) * dr : h[i];
+            for (int i = 0; i < kQ; ++i) h[i] = in ? wgt<T>(i) * dr : h[i];
+        }
     };
 
     // Stage plane p into LDS slot `slot`: densities of the own cell and of
