@@ -17,6 +17,13 @@
  *      is not stated, this is the reading taken).
  * Macroscopic outputs: u_macro of Eq. (HMCSC_u_macro) and p of Eq. (SC_pressure).
  *
+ * The alternative the paper contrasts with (Appendix, Guo vs. Shan-Chen
+ * forcing), forcing = HREF_FORCING_GUO: the grayscale scheme GS-WBS of
+ * Eq. (GS-WBS).  Steps 1 and 3 are the same; the equilibrium of every
+ * component is taken at u_macro of Eq. (HMCSC_u_macro) instead of step 4's
+ * velocity, and (1 - n_s) times the forcing term of Guo et al. (2002),
+ * evaluated with F_tot,sigma and u_macro, is added to the post-collision value.
+ *
  * Readings of the paper taken here (the paper is silent or ambiguous):
  *   - The interaction stencils of Eqs. (SC_F_inter), (SC_F_ads) weight the
  *     neighbours with g_scale*w_i.  g_scale = 1 is the literal text; g_scale = 3
@@ -119,6 +126,7 @@ static int check_params(const href_params* p, lattice_t* L)
     if (p->n_res < 0 || p->n_res > HREF_MAX_RES) return -1;
     for (int s = 0; s < p->ncomp; ++s)
         if (!(p->tau[s] > 0.5)) return -1;
+    if (p->forcing != HREF_FORCING_SHAN_CHEN && p->forcing != HREF_FORCING_GUO) return -1;
     for (int r = 0; r < p->n_res; ++r) {
         const href_reservoir* R = &p->res[r];
         if (R->axis < 0 || R->axis > 2 || R->lo < 0 || R->hi < R->lo) return -1;
@@ -158,8 +166,25 @@ static int reservoir_of(const href_params* p, int x, int y, int z)
 }
 
 /*
- * Local HMCSC collision at cell (x,y,z): post[s][i] is the right-hand side of
- * Eq. (LGS), i.e. what leaves the cell in direction i.  The densities of the
+ * Forcing term of Guo, Zheng and Shi (Phys. Rev. E 65, 046308, 2002), which
+ * the GS-WBS of Eq. (GS-WBS) uses, for direction i, force F and velocity u:
+ *   F_i = (1 - 1/(2 tau)) w_i [ (c_i - u).F / c_s^2 + (c_i.u)(c_i.F) / c_s^4 ].
+ */
+static double guo_term(const lattice_t* L, int i, double tau, const double u[3], const double F[3])
+{
+    double cF = 0.0, uF = 0.0, cu = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        cF += L->c[i][a] * F[a];
+        uF += u[a] * F[a];
+        cu += L->c[i][a] * u[a];
+    }
+    return (1.0 - 1.0 / (2.0 * tau)) * L->w[i] * ((cF - uF) / CS2 + cu * cF / (CS2 * CS2));
+}
+
+/*
+ * Local collision at cell (x,y,z): post[s][i] is the right-hand side of
+ * Eq. (LGS) (or of Eq. (GS-WBS) with Guo forcing), i.e. what leaves the cell
+ * in direction i.  The densities of the
  * neighbours come from rho_field when given, otherwise they are summed from f.
  * ftot (optional) receives F_tot,sigma.
  */
@@ -191,8 +216,9 @@ static void collide_at(const href_params* p, const lattice_t* L, const double* n
     }
     for (int a = 0; a < 3; ++a) up[a] = den > 0.0 ? num[a] / den : 0.0;
 
+    /* 3. total force per component */
+    double Ft[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     for (int s = 0; s < p->ncomp; ++s) {
-        const double nsx = ns_at(p, ns, s, n);
         double Finter[3] = {0.0, 0.0, 0.0}, Fads[3] = {0.0, 0.0, 0.0}, Fext[3];
 
         /* 3a. Eq. (SC_F_inter): -rho_s G sum_i W_i rho_sbar(x + c_i) c_i */
@@ -221,17 +247,34 @@ static void collide_at(const href_params* p, const lattice_t* L, const double* n
         /* 3c. Eq. (SC_F_ext) */
         for (int a = 0; a < 3; ++a) Fext[a] = rho > 0.0 ? rho_s[s] / rho * p->F_ext[a] : 0.0;
 
-        double Ft[3], ueq[3];
-        for (int a = 0; a < 3; ++a) Ft[a] = Finter[a] + Fads[a] + Fext[a];
+        for (int a = 0; a < 3; ++a) Ft[s][a] = Finter[a] + Fads[a] + Fext[a];
         if (ftot)
-            for (int a = 0; a < 3; ++a) ftot[s][a] = Ft[a];
+            for (int a = 0; a < 3; ++a) ftot[s][a] = Ft[s][a];
+    }
 
-        /* 4. Eq. (SC_u_eq) */
-        for (int a = 0; a < 3; ++a) ueq[a] = up[a] + (rho_s[s] > 0.0 ? p->tau[s] * Ft[a] / rho_s[s] : 0.0);
+    /* 4. velocity of the equilibrium: Eq. (SC_u_eq) for the HMCSC; for the
+     * GS-WBS with Guo forcing the macroscopic velocity of Eq. (HMCSC_u_macro),
+     * common to both components */
+    double um[3] = {0.0, 0.0, 0.0};
+    if (p->forcing == HREF_FORCING_GUO)
+        for (int a = 0; a < 3; ++a) {
+            double m = 0.0;
+            for (int s = 0; s < p->ncomp; ++s)
+                m += (1.0 - ns_at(p, ns, s, n)) * (j[s][a] + 0.5 * Ft[s][a]);
+            um[a] = rho > 0.0 ? m / rho : 0.0;
+        }
+
+    for (int s = 0; s < p->ncomp; ++s) {
+        const double nsx = ns_at(p, ns, s, n);
+        double ueq[3];
+        for (int a = 0; a < 3; ++a)
+            ueq[a] = p->forcing == HREF_FORCING_GUO
+                         ? um[a]
+                         : up[a] + (rho_s[s] > 0.0 ? p->tau[s] * Ft[s][a] / rho_s[s] : 0.0);
         if (ueq_out)
             for (int a = 0; a < 3; ++a) ueq_out[s][a] = ueq[a];
 
-        /* 5. Eq. (Maxwell) and Eq. (LGS) */
+        /* 5. Eq. (Maxwell) and Eq. (LGS), or Eq. (GS-WBS) with the Guo term */
         const double uu = ueq[0] * ueq[0] + ueq[1] * ueq[1] + ueq[2] * ueq[2];
         for (int i = 0; i < Q; ++i) {
             const double cu = L->c[i][0] * ueq[0] + L->c[i][1] * ueq[1] + L->c[i][2] * ueq[2];
@@ -239,6 +282,8 @@ static void collide_at(const href_params* p, const lattice_t* L, const double* n
                                (1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
             post[s][i] = (1.0 - nsx) * fl[s][i] - (1.0 - nsx) / p->tau[s] * (fl[s][i] - feq) +
                          nsx * fl[s][L->opp[i]];
+            if (p->forcing == HREF_FORCING_GUO)
+                post[s][i] += (1.0 - nsx) * guo_term(L, i, p->tau[s], ueq, Ft[s]);
         }
     }
 }

@@ -47,7 +47,13 @@ typedef struct {
     double F_ext[3];  /* external body force density                    */
     double g_scale;   /* interaction stencils weight neighbours by g_scale*w_i */
     href_reservoir res[HREF_MAX_RES];
+    int32_t forcing;  /* HREF_FORCING_SHAN_CHEN: the HMCSC, Eq. (HMCSC)           */
+                      /* HREF_FORCING_GUO: the GS-WBS with Guo forcing, Eq. (GS-WBS) */
+    int32_t pad;
 } href_params;
+
+#define HREF_FORCING_SHAN_CHEN 0
+#define HREF_FORCING_GUO 1
 
 /* Velocity set: q directions, c[3*i + a], weights w[i], opposite opp[i]. */
 int href_lattice(int32_t lattice, int32_t* q, int32_t* c, double* w, int32_t* opp);

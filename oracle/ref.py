@@ -52,7 +52,10 @@ class _Params(C.Structure):
                 ("ncomp", C.c_int32), ("c_ns", C.c_int32), ("n_res", C.c_int32),
                 ("nthreads", C.c_int32), ("tau", C.c_double * 2), ("G", C.c_double),
                 ("G_ads", C.c_double * 2), ("F_ext", C.c_double * 3), ("g_scale", C.c_double),
-                ("res", _Res * MAX_RES)]
+                ("res", _Res * MAX_RES), ("forcing", C.c_int32), ("pad", C.c_int32)]
+
+
+FORCING = {"shan-chen": 0, "guo": 1}
 
 
 @dataclass
@@ -77,6 +80,7 @@ class Setup:
     lattice: int = 19
     reservoirs: list = field(default_factory=list)
     nthreads: int = 0
+    forcing: str = "shan-chen"  # "guo": the GS-WBS with Guo forcing, Eq. (GS-WBS)
 
 
 def params_struct(s: Setup) -> _Params:
@@ -95,6 +99,7 @@ def params_struct(s: Setup) -> _Params:
     for a in range(3):
         p.F_ext[a] = s.F_ext[a]
     p.g_scale = s.g_scale
+    p.forcing = FORCING[s.forcing]
     for k, r in enumerate(s.reservoirs):
         p.res[k].axis, p.res[k].lo, p.res[k].hi = r.axis, r.lo, r.hi
         rr = list(r.rho) + [0.0] * (2 - len(r.rho))

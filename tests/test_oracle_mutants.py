@@ -18,7 +18,7 @@ from oracle import ref
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TESTS = os.path.join(ROOT, "tests")
 PINS = ["test_oracle_forces.py", "test_oracle_closed_forms.py", "test_oracle_invariants.py",
-        "test_oracle_lattice.py", "test_oracle_shear_wave.py", "test_oracle_brinkman.py"]
+        "test_oracle_lattice.py", "test_oracle_shear_wave.py", "test_oracle_brinkman.py", "test_oracle_guo.py"]
 
 # (name, text in hmcsc_oracle.c, replacement, which occurrence (1-based))
 MUTANTS = [
@@ -37,7 +37,7 @@ MUTANTS = [
     ("bounce-back blend without 1 - n_s", "post[s][i] = (1.0 - nsx) * fl[s][i]", "post[s][i] = fl[s][i]", 1),
     ("second-order term of the equilibrium doubled", "(cu * cu) / (2.0 * CS2 * CS2)", "(cu * cu) / (CS2 * CS2)", 1),
     ("velocity term of the equilibrium halved", "1.0 + cu / CS2", "1.0 + cu / (2.0 * CS2)", 1),
-    ("force shift without tau", "p->tau[s] * Ft[a] / rho_s[s]", "Ft[a] / rho_s[s]", 1),
+    ("force shift without tau", "p->tau[s] * Ft[s][a] / rho_s[s]", "Ft[s][a] / rho_s[s]", 1),
     ("common velocity not tau-weighted", "num[a] += j[s][a] / p->tau[s];", "num[a] += j[s][a];", 1),
     ("macroscopic velocity without the half force", "(js + Ft[s][a] / 2.0)", "(js + Ft[s][a])", 1),
     ("macroscopic velocity not weighted by 1 - n_s", "m += (1.0 - ns_at(p, ns, s, n)) * (js", "m += (js", 1),
@@ -45,6 +45,14 @@ MUTANTS = [
     ("axis weight 1/16", "w1 = 1.0 / 18.0;", "w1 = 1.0 / 16.0;", 1),
     ("stencil scale ignored", "g[a] += p->g_scale * L->w[i] * r_nb * L->c[i][a];",
      "g[a] += L->w[i] * r_nb * L->c[i][a];", 1),
+    # the GS-WBS with Guo forcing
+    ("Guo term without its second-order part", "((cF - uF) / CS2 + cu * cF / (CS2 * CS2))",
+     "((cF - uF) / CS2)", 1),
+    ("Guo term without its velocity part", "((cF - uF) / CS2", "((cF) / CS2", 1),
+    ("Guo prefactor dropped", "(1.0 - 1.0 / (2.0 * tau)) * L->w[i]", "L->w[i]", 1),
+    ("Guo term not weighted by 1 - n_s", "post[s][i] += (1.0 - nsx) * guo_term(", "post[s][i] += guo_term(", 1),
+    ("Guo velocity without the half force", "(j[s][a] + 0.5 * Ft[s][a])", "(j[s][a])", 1),
+    ("Guo velocity not weighted by 1 - n_s", "m += (1.0 - ns_at(p, ns, s, n)) * (j[s][a]", "m += (j[s][a]", 1),
 ]
 
 
