@@ -9,7 +9,9 @@ sum_i W_i c_i c_i = I).  A step is one full time step of the method over the
 whole domain (forces, collision, partial bounce-back, streaming, reservoirs).
 
 Headline value: MLUPS of the plain FP32 path.  The same workload is also timed
-with shifted FP16 and BF16 storage (FP32 arithmetic).  Each variant reports
+with shifted FP16 and BF16 storage (FP32 arithmetic), and in FP32 with the
+GS-WBS of the paper's appendix (Guo forcing, Eq. GS-WBS; same bytes per cell,
+both components' forces evaluated per cell).  Each variant reports
 its step kernel against the HBM roofline, with the algorithmic bytes per cell
 update B = 2*19*2*s + 4 (read and write every population once, read n_s once).
 
@@ -62,11 +64,13 @@ def traffic_for(storage: str):
     return None if v is None else v.get("bytes_per_launch")
 
 
-def run_variant(w, storage, steps, warmup):
+def run_variant(w, variant, steps, warmup):
+    """variant: a storage name, or storage-guo for the GS-WBS with Guo forcing."""
     import torch
     from paper_2206_11524_amd import lbm
 
-    sim = lbm.from_workload(w, storage=storage)
+    storage, _, scheme = variant.partition("-")
+    sim = lbm.from_workload(w, storage=storage, forcing="guo" if scheme == "guo" else "shan-chen")
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -84,7 +88,7 @@ def run_variant(w, storage, steps, warmup):
     mlups = N * steps / dt / 1e6
     B = alg_bytes(storage, w.ncomp, w.c_ns)
     achieved = B * N / (kernel_ms * 1e-3) / 1e9
-    traffic = traffic_for(storage)
+    traffic = traffic_for(variant)
     return {
         "storage": storage,
         "mlups": mlups,
@@ -227,7 +231,8 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--edge", type=int, default=256)
-    ap.add_argument("--variants", default="f32,f16s,bf16s")
+    ap.add_argument("--variants", default="f32,f16s,bf16s,f32-guo",
+                    help="storage formats; storage-guo runs the GS-WBS with Guo forcing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-ensemble", action="store_true")

@@ -64,6 +64,18 @@ typedef enum {
     LBM_ROUND_STOCHASTIC = 1
 } lbm_rounding;
 
+/* Collision and forcing scheme.  LBM_FORCING_SHAN_CHEN is the HMCSC of
+ * Eq. (HMCSC) / Eq. (LGS): the forces enter through the force-shifted
+ * equilibrium velocity of Eq. (SC_u_eq).  LBM_FORCING_GUO is the grayscale
+ * scheme the paper contrasts it with (appendix on Guo vs. Shan-Chen forcing,
+ * Eq. GS-WBS): equilibrium at u_macro of Eq. (HMCSC_u_macro) plus (1 - n_s)
+ * times the forcing term of Guo, Zheng and Shi (2002).  The GS-WBS runs with
+ * the default tile shapes and is not accepted by the batched server. */
+typedef enum {
+    LBM_FORCING_SHAN_CHEN = 0,
+    LBM_FORCING_GUO = 1
+} lbm_forcing;
+
 typedef struct {
     int32_t nx, ny, nz;
 } lbm_domain;
@@ -94,7 +106,7 @@ typedef struct {
     int32_t n_res;            /* number of reservoirs, 0..LBM_MAX_RES                   */
     int32_t check_every;      /* health check (finite mass) every k steps; 0 = never    */
     int32_t rounding;         /* lbm_rounding (16-bit formats)                          */
-    int32_t pad;
+    int32_t forcing;          /* lbm_forcing                                            */
     lbm_reservoir res[LBM_MAX_RES];
 } lbm_params;
 
@@ -245,7 +257,7 @@ typedef struct lbm_group lbm_group;
 /* Group the n contexts ctxs[0..n-1] (caller keeps ownership; they must
  * outlive the group and not be stepped on their own meanwhile).  Work is
  * queued on the stream of ctxs[0].  LBM_EINVAL if they differ in storage,
- * ncomp or c_ns, or n < 1. */
+ * ncomp or c_ns, if any uses LBM_FORCING_GUO, or n < 1. */
 int lbm_group_create(lbm_ctx* const* ctxs, int32_t n, lbm_group** out);
 
 /* Advance every context of the group by nsteps (asynchronous; launches are
@@ -318,8 +330,8 @@ typedef struct {
 /* Create a server on the current device.  reserved must be NULL. */
 int lbm_server_create(const lbm_server_cfg* cfg, void* reserved, lbm_server** out);
 
-/* Queue a request; *ticket identifies it.  LBM_EINVAL for invalid input or a
- * format mismatch, LBM_ENOMEM if its state can never fit the budget or it
+/* Queue a request; *ticket identifies it.  LBM_EINVAL for invalid input, a
+ * format mismatch or LBM_FORCING_GUO, LBM_ENOMEM if its state can never fit the budget or it
  * exceeds max_cells. Thread-safe. */
 int lbm_batch_submit(lbm_server* s, const lbm_request* req, uint64_t* ticket);
 

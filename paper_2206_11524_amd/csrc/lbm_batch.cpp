@@ -213,7 +213,8 @@ int lbm_group_create(lbm_ctx* const* ctxs, int32_t n, lbm_group** out)
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return LBM_EINVAL;
         if (ctxs[i]->prm.storage != ctxs[0]->prm.storage || ctxs[i]->prm.ncomp != ctxs[0]->prm.ncomp ||
-            ctxs[i]->prm.c_ns != ctxs[0]->prm.c_ns || ctxs[i]->device != ctxs[0]->device)
+            ctxs[i]->prm.c_ns != ctxs[0]->prm.c_ns || ctxs[i]->device != ctxs[0]->device ||
+            ctxs[i]->prm.forcing != LBM_FORCING_SHAN_CHEN)  // the batched kernel runs the HMCSC only
             return LBM_EINVAL;
     }
     lbm_group* g = new (std::nothrow) lbm_group();
@@ -547,6 +548,7 @@ int lbm_batch_submit(lbm_server* s, const lbm_request* rq, uint64_t* ticket)
     if (p.storage != s->cfg.storage || p.ncomp != s->cfg.ncomp || p.c_ns != s->cfg.c_ns) return LBM_EINVAL;
     if (rq->max_steps < 1 || !(rq->conv_tol >= 0.0) || !rq->n_s || !rq->rho_init) return LBM_EINVAL;
     if (p.check_every != 0) return LBM_EINVAL;
+    if (p.forcing != LBM_FORCING_SHAN_CHEN) return LBM_EINVAL;  // the batched kernel runs the HMCSC only
     lbm_sizes sz{};
     const int vrc = lbm_required_bytes(&rq->dom, &p, &sz);
     if (vrc) return vrc;

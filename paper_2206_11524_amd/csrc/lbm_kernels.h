@@ -9,6 +9,8 @@ namespace hm {
 
 constexpr int kQ = 19;
 constexpr int kMaxRes = 4;
+constexpr int kForcingShanChen = 0;  // Eq. (HMCSC)
+constexpr int kForcingGuo = 1;       // Eq. (GS-WBS)
 
 enum Storage { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
@@ -26,6 +28,7 @@ struct Problem {
     double rho0[2];
     double scale;      // 2^store_scale_log2
     int stochastic;    // 16-bit formats: stochastic rounding of stored values
+    int forcing;       // kForcingShanChen (the HMCSC) or kForcingGuo (the GS-WBS)
     double g_scale, G_inter;
     int n_res;
     int res_axis[kMaxRes], res_lo[kMaxRes], res_hi[kMaxRes];

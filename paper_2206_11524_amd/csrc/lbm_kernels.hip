@@ -184,6 +184,7 @@ struct Args {
     T F[3];
     T rho0[2];
     T scale, inv_scale;
+    T guo[2];    // 1 - 1/(2 tau): weight of the Guo forcing term (GS-WBS)
     int sr;      // stochastic rounding of stored values
     uint32_t t;  // time step of the state read by the launch (single-domain launches)
     int n_res;
@@ -200,6 +201,7 @@ static Args<T> make_args(const Problem& p)
     for (int s = 0; s < 2; ++s) {
         a.tau[s] = static_cast<T>(p.tau[s]);
         a.inv_tau[s] = static_cast<T>(1.0 / p.tau[s]);
+        a.guo[s] = static_cast<T>(1.0 - 0.5 / p.tau[s]);
         a.Gads_s[s] = static_cast<T>(p.Gads_s[s]);
         a.rho0[s] = static_cast<T>(p.rho0[s]);
     }
@@ -431,6 +433,52 @@ __device__ __forceinline__ void cell_velocity(const Args<T>& a, int s, int me, c
     n = static_cast<T>(ns_0[cn * LP + me]);
 }
 
+// The GS-WBS of Eq. (GS-WBS) takes its equilibrium at u_macro of
+// Eq. (HMCSC_u_macro), common to the components: sum_c (1 - n_c)(j_c +
+// F_tot,c / 2) / rho.  That needs the total force of every component at the
+// cell (both cohesion stencils); returns u_macro, the own total force, the own
+// density and n_s.
+template <typename T, int NC, int CNS, int LW, int LP>
+__device__ __forceinline__ void cell_velocity_guo(const Args<T>& a, int s, int me, const T* rho_m, const T* rho_0,
+                                                  const T* rho_p, const float* ns_m, const float* ns_0,
+                                                  const float* ns_p, const T (&jc)[NC][3], T um[3], T fo[3],
+                                                  T& rho_own, T& n_own)
+{
+    T rc[NC], rho = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        rc[c] = rho_0[c * LP + me];
+        rho += rc[c];
+    }
+    const T inv_rho = rho > T(0) ? recip(rho) : T(0);
+    T m[3] = {0, 0, 0};
+    T ga[3];
+    if constexpr (CNS == 1) stencil<T, float, LW>(ns_m, ns_0, ns_p, me, ga);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int cn = CNS == 2 ? c : 0;
+        if constexpr (CNS == 2) stencil<T, float, LW>(ns_m + cn * LP, ns_0 + cn * LP, ns_p + cn * LP, me, ga);
+        T gi[3] = {0, 0, 0};
+        if constexpr (NC == 2)
+            stencil<T, T, LW>(rho_m + (1 - c) * LP, rho_0 + (1 - c) * LP, rho_p + (1 - c) * LP, me, gi);
+        const T nc = static_cast<T>(ns_0[cn * LP + me]);
+        T F[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            F[d] = rc[c] * (-a.G_s * gi[d] - a.Gads_s[c] * ga[d] + a.F[d] * inv_rho);
+            m[d] += (T(1) - nc) * (jc[c][d] + T(0.5) * F[d]);
+        }
+        if (c == s) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) fo[d] = F[d];
+            rho_own = rc[c];
+            n_own = nc;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) um[d] = m[d] * inv_rho;
+}
+
 // Force-shifted BGK collision blended with partial bounce-back, Eq. (LGS), in
 // the shifted variables: post_i = (1-n)(h_i - (h_i - h^eq_i)/tau_s) + n h_ibar
 // with h^eq from Eq. (Maxwell) at u_eq (the w_i rho0 shift cancels because
@@ -486,6 +534,52 @@ __device__ __forceinline__ void relax_dir(const RelaxCoef<T>& k, int i, T hi, T 
     post_o = k.ca * ho + (k.n * hi + (t - e));
 }
 
+// The forcing term of Guo, Zheng and Shi (2002), weighted by (1 - n_s) as in
+// Eq. (GS-WBS): F_i = A w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)] with
+// A = (1 - n)(1 - 1/(2 tau)).  For a pair (i, ibar) the part even in c_i,
+// A w (9 cu cF - 3 u.F), adds to both, the odd part A w 3 cF with opposite
+// signs, as in relax_dir.
+template <typename T>
+struct GuoCoef {
+    T gw[3];   // A w per weight class
+    T f[3];    // F_tot of the component
+    T uF;
+};
+
+template <typename T>
+__device__ __forceinline__ GuoCoef<T> guo_coef(const Args<T>& a, int s, T n, const T F[3], const T u[3])
+{
+    GuoCoef<T> g;
+    const T A = (T(1) - n) * a.guo[s];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g.gw[c] = A * (c == 0 ? T(1) / T(3) : (c == 1 ? T(1) / T(18) : T(1) / T(36)));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g.f[d] = F[d];
+    g.uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    return g;
+}
+
+template <typename T>
+__device__ __forceinline__ T relax_rest_guo(const RelaxCoef<T>& k, const GuoCoef<T>& g, T h0)
+{
+    return k.ca * h0 + k.n * h0 + (k.K0[0] + g.gw[0] * (T(-3) * g.uF));
+}
+
+template <typename T>
+__device__ __forceinline__ void relax_dir_guo(const RelaxCoef<T>& k, const GuoCoef<T>& g, int i, T hi, T ho,
+                                              T& post_i, T& post_o)
+{
+    const int c = (CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]) == 1 ? 1 : 2;
+    T cu = T(0), cF = T(0);
+    if (CX[i]) { cu += CX[i] > 0 ? k.u[0] : -k.u[0]; cF += CX[i] > 0 ? g.f[0] : -g.f[0]; }
+    if (CY[i]) { cu += CY[i] > 0 ? k.u[1] : -k.u[1]; cF += CY[i] > 0 ? g.f[1] : -g.f[1]; }
+    if (CZ[i]) { cu += CZ[i] > 0 ? k.u[2] : -k.u[2]; cF += CZ[i] > 0 ? g.f[2] : -g.f[2]; }
+    const T t = k.K2[c] * (cu * cu) + k.K0[c] + g.gw[c] * (T(9) * (cu * cF) - T(3) * g.uF);
+    const T e = k.K1[c] * cu + g.gw[c] * (T(3) * cF);
+    post_i = k.ca * hi + (k.n * ho + (t + e));
+    post_o = k.ca * ho + (k.n * hi + (t - e));
+}
+
 // One thread per (cell, component): a block of NC*TX*TY threads owns a TX x TY
 // column of cells; threads [s*TX*TY, (s+1)*TX*TY) handle component s.  The two
 // components of a cell meet only through LDS (densities and first moments),
@@ -516,7 +610,7 @@ struct TileShared {
 
 // The sweep of one tile column (logical tile index L of the domain described
 // by a).  Shared by the single-domain and the batched kernels.
-template <typename ST, int NC, int CNS, int TX, int TY>
+template <typename ST, int NC, int CNS, int TX, int TY, int FS>
 __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const typename ST::E* __restrict__ A,
                                           typename ST::E* __restrict__ B, const float* __restrict__ ns, int L,
                                           uint32_t t, TileShared<ST, NC, CNS, TX, TY>& sh)
@@ -671,32 +765,47 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                 for (int d = 0; d < 3; ++d) jc[c][d] = s_j[js][c][d][tj];
             }
         }
-        T ueq[3], rho_own, n;
-        cell_velocity<T, NC, CNS, LW, LP>(a, s, me, &s_rho[sm][0][0], &s_rho[s0][0][0], &s_rho[sp][0][0],
-                                          &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, ueq, rho_own, n);
+        T ueq[3], rho_own, n, fo[3];
+        if constexpr (FS == kForcingGuo)
+            cell_velocity_guo<T, NC, CNS, LW, LP>(a, s, me, &s_rho[sm][0][0], &s_rho[s0][0][0], &s_rho[sp][0][0],
+                                                  &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, ueq, fo,
+                                                  rho_own, n);
+        else
+            cell_velocity<T, NC, CNS, LW, LP>(a, s, me, &s_rho[sm][0][0], &s_rho[s0][0][0], &s_rho[sp][0][0],
+                                              &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, ueq, rho_own, n);
         const uint32_t zo = static_cast<uint32_t>(z) * plane_bytes;
         const RelaxCoef<T> k = relax_coef<T>(a, s, rho_own, ueq, n);
+        GuoCoef<T> g{};
+        if constexpr (FS == kForcingGuo) g = guo_coef<T>(a, s, n, fo, ueq);
+        auto rest = [&]() {
+            if constexpr (FS == kForcingGuo) return relax_rest_guo(k, g, h[0]);
+            else return relax_rest(k, h[0]);
+        };
+        auto pair = [&](int i, T& pi, T& po) {
+            if constexpr (FS == kForcingGuo) relax_dir_guo(k, g, i, h[i], h[i + 9], pi, po);
+            else relax_dir(k, i, h[i], h[i + 9], pi, po);
+        };
         if (a.sr) {
             // counter: (cell, component) mixed with the time step, then the direction
             // 32 random bits per direction pair (i, i+9), 16 for each value:
             // fmix32 of (cell, component, time), then xorshift32 steps
             const uint32_t cell = static_cast<uint32_t>(z * plane + y * a.nx + x);
             uint32_t r = fmix32(t_key ^ (2u * cell + static_cast<uint32_t>(s))) | 1u;  // nonzero state
-            ST::bst(ST::enc_sr(relax_rest(k, h[0]), a.scale, r >> 16), rb, own, zo);
+            ST::bst(ST::enc_sr(rest(), a.scale, r >> 16), rb, own, zo);
 #pragma unroll
             for (int i = 1; i <= 9; ++i) {
                 T pi, po;
-                relax_dir(k, i, h[i], h[i + 9], pi, po);
+                pair(i, pi, po);
                 r = xorshift32(r);
                 ST::bst(ST::enc_sr(pi, a.scale, r & 0xffffu), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
                 ST::bst(ST::enc_sr(po, a.scale, r >> 16), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
             }
         } else {
-            ST::bst(ST::enc(relax_rest(k, h[0]), a.scale), rb, own, zo);
+            ST::bst(ST::enc(rest(), a.scale), rb, own, zo);
 #pragma unroll
             for (int i = 1; i <= 9; ++i) {
                 T pi, po;
-                relax_dir(k, i, h[i], h[i + 9], pi, po);
+                pair(i, pi, po);
                 ST::bst(ST::enc(pi, a.scale), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
                 ST::bst(ST::enc(po, a.scale), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
             }
@@ -829,7 +938,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     }
 }
 
-template <typename ST, int NC, int CNS, int TX, int TY>
+template <typename ST, int NC, int CNS, int TX, int TY, int FS>
 __global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
                                                       const typename ST::E* __restrict__ A,
                                                       typename ST::E* __restrict__ B,
@@ -841,7 +950,7 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
     const int nb = gridDim.x;
     int L = blockIdx.x;
     if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    step_tile<ST, NC, CNS, TX, TY>(a, A, B, ns, L, a.t, sh);
+    step_tile<ST, NC, CNS, TX, TY, FS>(a, A, B, ns, L, a.t, sh);
 }
 
 
@@ -893,7 +1002,7 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step_batch(const char* __restric
         if (k >= e.steps) continue;
         const int cur = (e.parity + k) & 1;
         __syncthreads();  // the previous tile's LDS is no longer read
-        step_tile<ST, NC, CNS, TX, TY>(e.a, static_cast<const E*>(e.buf[cur]), static_cast<E*>(const_cast<void*>(e.buf[1 - cur])),
+        step_tile<ST, NC, CNS, TX, TY, kForcingShanChen>(e.a, static_cast<const E*>(e.buf[cur]), static_cast<E*>(const_cast<void*>(e.buf[1 - cur])),
                                        e.ns, w - e.tile_begin, e.a.t + static_cast<uint32_t>(k), sh);
     }
 }
@@ -1150,7 +1259,7 @@ int storage_bytes(int storage)
     }
 }
 
-template <typename ST, int NC, int CNS, int TX, int TY>
+template <typename ST, int NC, int CNS, int TX, int TY, int FS>
 static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
                          hipStream_t st)
 {
@@ -1163,7 +1272,7 @@ static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const voi
     a.nzc = (p.nz + l.zchunk - 1) / l.zchunk;
     a.t = static_cast<uint32_t>(t);
     const int nblocks = a.ntx * a.nty * a.nzc;
-    hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY>), dim3(nblocks), dim3(NC * TX * TY), 0, st, a,
+    hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS>), dim3(nblocks), dim3(NC * TX * TY), 0, st, a,
                        static_cast<const E*>(A), static_cast<E*>(B), ns);
     return hipGetLastError();
 }
@@ -1173,12 +1282,18 @@ template <typename ST, int NC, int CNS>
 static hipError_t step_ty(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
                           hipStream_t st)
 {
-    if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16>(p, l, t, A, B, ns, st);
+    constexpr int SC = kForcingShanChen, GUO = kForcingGuo;
+    if (p.forcing == kForcingGuo) {  // the GS-WBS: the default tiles only
+        if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8, GUO>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4, GUO>(p, l, t, A, B, ns, st);
+        return hipErrorInvalidValue;
+    }
+    if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4, SC>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4, SC>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8, SC>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4, SC>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8, SC>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16, SC>(p, l, t, A, B, ns, st);
     return hipErrorInvalidValue;
 }
 

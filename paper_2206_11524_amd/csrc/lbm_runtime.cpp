@@ -48,6 +48,7 @@ int validate(const lbm_domain* d, const lbm_params* p)
     }
     if (p->check_every < 0) return LBM_EINVAL;
     if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC) return LBM_EINVAL;
+    if (p->forcing != LBM_FORCING_SHAN_CHEN && p->forcing != LBM_FORCING_GUO) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -68,6 +69,7 @@ hm::Problem make_problem(const lbm_domain* d, const lbm_params* p)
     for (int a = 0; a < 3; ++a) q.F[a] = p->F_ext[a];
     q.scale = std::ldexp(1.0, p->store_scale_log2);
     q.stochastic = (p->storage == LBM_F16S || p->storage == LBM_BF16S) && p->rounding == LBM_ROUND_STOCHASTIC;
+    q.forcing = p->forcing == LBM_FORCING_GUO ? hm::kForcingGuo : hm::kForcingShanChen;
     q.n_res = p->n_res;
     for (int r = 0; r < hm::kMaxRes; ++r) {
         if (r < p->n_res) {
@@ -97,7 +99,9 @@ hm::Launch choose_launch(const hm::Problem& p, int cus)
     const bool wide = p.storage == hm::kF64 && p.ncomp == 2;
     l.tile_x = env_int("LBM_TILE_X", 64);
     l.tile_y = env_int("LBM_TILE_Y", (p.ny >= 8 && !wide) ? 8 : 4);
-    if (!hm::tile_supported(l.tile_x, l.tile_y)) {
+    // the GS-WBS is compiled for the default tiles only
+    if (!hm::tile_supported(l.tile_x, l.tile_y) ||
+        (p.forcing == hm::kForcingGuo && !(l.tile_x == 64 && (l.tile_y == 8 || l.tile_y == 4)))) {
         l.tile_x = 64;
         l.tile_y = wide ? 4 : 8;
     }

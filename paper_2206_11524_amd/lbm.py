@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("G_inter", C.c_double), ("G_ads", C.c_double * 2), ("F_ext", C.c_double * 3),
                 ("g_scale", C.c_double), ("rho_shift", C.c_double * 2), ("storage", C.c_int32),
                 ("store_scale_log2", C.c_int32), ("n_res", C.c_int32), ("check_every", C.c_int32),
-                ("rounding", C.c_int32), ("pad", C.c_int32), ("res", Reservoir * MAX_RES)]
+                ("rounding", C.c_int32), ("forcing", C.c_int32), ("res", Reservoir * MAX_RES)]
 
 
 class Sizes(C.Structure):
@@ -125,6 +125,8 @@ def default_shift(storage: str, ncomp: int, rho_init: np.ndarray):
 
 
 ROUNDING = {"nearest": 0, "stochastic": 1}
+# "shan-chen": the HMCSC; "guo": the GS-WBS with Guo forcing (Eq. GS-WBS)
+FORCING = {"shan-chen": 0, "guo": 1}
 
 
 def default_rounding(storage: str) -> str:
@@ -135,7 +137,7 @@ def default_rounding(storage: str) -> str:
 
 def make_params(ncomp=2, c_ns=1, tau=(1.0, 1.0), G=0.0, G_ads=(0.0, 0.0), F_ext=(0.0, 0.0, 0.0),
                 g_scale=1.0, storage="f64", rho_shift=(0.0, 0.0), store_scale_log2=0,
-                reservoirs: Sequence = (), check_every=0, rounding=None) -> Params:
+                reservoirs: Sequence = (), check_every=0, rounding=None, forcing="shan-chen") -> Params:
     p = Params()
     p.ncomp, p.c_ns = ncomp, c_ns
     t = list(tau) + [1.0] * (2 - len(tau))
@@ -157,6 +159,7 @@ def make_params(ncomp=2, c_ns=1, tau=(1.0, 1.0), G=0.0, G_ads=(0.0, 0.0), F_ext=
         p.res[k].rho[0], p.res[k].rho[1] = rr[0], rr[1]
     p.check_every = check_every
     p.rounding = ROUNDING[rounding or default_rounding(storage)]
+    p.forcing = FORCING[forcing]
     return p
 
 
@@ -286,14 +289,14 @@ class Simulation:
 
 
 def from_workload(w, storage="f32", rho_shift=None, store_scale_log2=0, check_every=0, rounding=None,
-                  **kw) -> Simulation:
+                  forcing="shan-chen", **kw) -> Simulation:
     """Simulation of an ``inputs.Workload``."""
     if rho_shift is None:
         rho_shift = default_shift(storage, w.ncomp, w.rho)
     p = make_params(ncomp=w.ncomp, c_ns=w.c_ns, tau=w.tau, G=w.G, G_ads=w.G_ads, F_ext=w.F_ext,
                     g_scale=w.g_scale, storage=storage, rho_shift=rho_shift,
                     store_scale_log2=store_scale_log2, reservoirs=w.reservoirs, check_every=check_every,
-                    rounding=rounding)
+                    rounding=rounding, forcing=forcing)
     return Simulation(w.shape, w.ns, w.rho, p, **kw)
 
 

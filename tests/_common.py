@@ -5,11 +5,11 @@ import numpy as np
 from oracle.ref import Oracle, Reservoir, Setup
 
 
-def oracle_for(w, nthreads=0):
+def oracle_for(w, nthreads=0, forcing="shan-chen"):
     res = [Reservoir(a, lo, hi, tuple(r)) for (a, lo, hi, r) in w.reservoirs]
     st = Setup(w.shape, ncomp=w.ncomp, c_ns=w.c_ns, tau=tuple(w.tau) + (1.0,) * (2 - len(w.tau)),
                G=w.G, G_ads=w.G_ads, F_ext=w.F_ext, g_scale=w.g_scale, reservoirs=res,
-               nthreads=nthreads)
+               nthreads=nthreads, forcing=forcing)
     return Oracle(st, w.ns.astype(np.float64))
 
 

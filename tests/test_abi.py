@@ -79,6 +79,14 @@ def test_invalid_rounding_mode_rejected(lib):
     assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_EINVAL
 
 
+def test_invalid_forcing_scheme_rejected(lib):
+    p = lbm.make_params(ncomp=2, c_ns=1, storage="f32", forcing="guo")
+    d, s = lbm.Domain(8, 8, 8), lbm.Sizes()
+    assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_OK
+    p.forcing = 2
+    assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_EINVAL
+
+
 _STRUCTS = ["lbm_domain", "lbm_reservoir", "lbm_params", "lbm_sizes", "lbm_device_buffers", "lbm_totals",
             "lbm_fill_query", "lbm_fill_state", "lbm_server_cfg", "lbm_request", "lbm_result", "lbm_server_stats"]
 
