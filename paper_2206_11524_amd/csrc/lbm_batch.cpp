@@ -97,15 +97,22 @@ class BatchRunner {
         // z-chunks from the batch as a whole: about four tiles per CU, no
         // tile longer than 32 planes (blocks stride over tiles of unequal
         // domains, short tiles balance them), none shorter than 16 (each
-        // chunk re-reads two halo planes)
+        // chunk re-reads two halo planes) unless the batch would then give
+        // fewer than two tiles per CU: a few small domains alone would leave
+        // most of the GPU idle, and the halo re-reads cost little there
         balanced_.assign(d, d + n);
-        int64_t cols = 0;
-        for (const hm::BatchDomain& b : balanced_)
-            cols += static_cast<int64_t>((b.prob.nx + tx_ - 1) / tx_) * ((b.prob.ny + ty_ - 1) / ty_);
+        int64_t cols = 0, tiles16 = 0;
+        for (const hm::BatchDomain& b : balanced_) {
+            const int64_t c = static_cast<int64_t>((b.prob.nx + tx_ - 1) / tx_) * ((b.prob.ny + ty_ - 1) / ty_);
+            cols += c;
+            tiles16 += c * ((b.prob.nz + 15) / 16);
+        }
+        const int64_t min_chunk = tiles16 >= 2 * static_cast<int64_t>(cus_) ? 16 : 4;
         const int64_t per_cols = std::max<int64_t>(1, (4 * static_cast<int64_t>(cus_) + cols - 1) / std::max<int64_t>(cols, 1));
         for (hm::BatchDomain& b : balanced_) {
             const int64_t chunks = std::max<int64_t>(per_cols, (b.prob.nz + 31) / 32);
-            b.zchunk = static_cast<int>(std::min<int64_t>(b.prob.nz, std::max<int64_t>(16, (b.prob.nz + chunks - 1) / chunks)));
+            b.zchunk = static_cast<int>(
+                std::min<int64_t>(b.prob.nz, std::max<int64_t>(min_chunk, (b.prob.nz + chunks - 1) / chunks)));
         }
         hm::batch_encode(storage_, balanced_.data(), n, tx_, ty_, host_[j]);
         HIP_TRY(hipMemcpyAsync(dev_[j], host_[j], bytes_, hipMemcpyHostToDevice, stream_));
