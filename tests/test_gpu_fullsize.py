@@ -61,12 +61,13 @@ def _sample_cells(w, seed=5):
     return np.unique(cells)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16s"])
-def test_one_step_at_full_size(electrode, storage):
+@pytest.mark.parametrize("storage,forcing", [("f32", "shan-chen"), ("f16s", "shan-chen"), ("f32", "guo")])
+def test_one_step_at_full_size(electrode, storage, forcing):
+    """(forcing = "guo": the GS-WBS kernel against the oracle's GS-WBS)"""
     import oracle
     _, w19, _ = oracle.lattice(19)
     w = electrode
-    sim = lbm.from_workload(w, storage=storage)
+    sim = lbm.from_workload(w, storage=storage, forcing=forcing)
     sim.step(3)
     f_t = sim.populations()
     sim.step(1)
@@ -74,7 +75,7 @@ def test_one_step_at_full_size(electrode, storage):
     rho0 = np.array(lbm.default_shift(storage, 2, w.rho))[:2]
     sim.close()
     cells = _sample_cells(w)
-    o = oracle_for(w)
+    o = oracle_for(w, forcing=forcing)
     ref = o.cell_update(f_t, cells)                       # [k, s, i]
     got = f_t1.reshape(2, 19, -1)[:, :, cells].transpose(2, 0, 1)
     h_ref = ref - w19[None, None, :] * rho0[None, :, None]
