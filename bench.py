@@ -225,6 +225,34 @@ def cpu_baseline(w, budget_s=20.0):
                       f"FP64, {dt:.1f} s"}
 
 
+def cpu_baseline_single_thread(w, planes=16, budget_s=6.0):
+    """The FP64 oracle on one host thread: whole steps of a slab of the same
+    workload (planes z in [nz/2 - planes/2, nz/2 + planes/2), periodic, away
+    from the reservoirs), bounded to a few seconds."""
+    from oracle.ref import Oracle, Setup
+
+    nx, ny, nz = w.shape
+    z0 = max(0, nz // 2 - planes // 2)
+    z1 = min(nz, z0 + planes)
+    ns = np.ascontiguousarray(w.ns[:, z0:z1].astype(np.float64))
+    rho = np.ascontiguousarray(w.rho[:, z0:z1])
+    st = Setup((nx, ny, z1 - z0), ncomp=w.ncomp, c_ns=w.c_ns, tau=w.tau, G=w.G, G_ads=w.G_ads, F_ext=w.F_ext,
+               g_scale=w.g_scale, nthreads=1)
+    o = Oracle(st, ns)
+    f = o.init(rho)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f = o.step(f)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 20:
+            break
+    dt = time.perf_counter() - t0
+    cells = nx * ny * (z1 - z0)
+    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full time steps of a {nx}x{ny}x{z1 - z0} slab of the workload, FP64, {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +337,8 @@ def main():
     line["roofline"]["frac_of_stream_copy"] = round(head["roofline"]["achieved"] / copy, 4)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        print(f"# cpu baseline: {line['cpu_baseline']}", file=sys.stderr, flush=True)
+        line["cpu_baseline_1thread"] = cpu_baseline_single_thread(w)
     print(json.dumps(line), flush=True)
 
 
