@@ -110,10 +110,10 @@ hm::Launch choose_launch(const hm::Problem& p, int cus)
     const int64_t cols = static_cast<int64_t>(ntx) * nty;
     int zc = env_int("LBM_ZCHUNK", 0);
     if (zc <= 0) {
-        // One block fits a CU (registers), so aim at one z-chunk per CU and
-        // column: every block is resident from the start and none waits for
-        // a second round.  Chunks shorter than 16 planes would spend too much
-        // on their two halo planes.
+        // One block fits a CU (registers and LDS), so aim at one z-chunk per
+        // CU and column: every block is resident from the start and none
+        // waits for a CU to free up.  Chunks shorter than 16 planes would
+        // spend too much on their two halo planes.
         const int64_t chunks = std::max<int64_t>(1, std::max(cus, 1) / cols);
         zc = static_cast<int>(std::max<int64_t>(16, (p.nz + chunks - 1) / chunks));
     }
