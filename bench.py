@@ -9,7 +9,7 @@ sum_i W_i c_i c_i = I).  A step is one full time step of the method over the
 whole domain (forces, collision, partial bounce-back, streaming, reservoirs).
 
 Headline value: MLUPS of the plain FP32 path.  The same workload is also timed
-with shifted FP16 and BF16 storage (FP32 arithmetic), and in FP32 with the
+with shifted FP16 and BF16 storage (FP32 arithmetic), in FP64, and in FP32 with the
 GS-WBS of the paper's appendix (Guo forcing, Eq. GS-WBS; same bytes per cell,
 both components' forces evaluated per cell).  Each variant reports
 its step kernel against the HBM roofline, with the algorithmic bytes per cell
@@ -259,7 +259,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--edge", type=int, default=256)
-    ap.add_argument("--variants", default="f32,f16s,bf16s,f32-guo",
+    ap.add_argument("--variants", default="f32,f16s,bf16s,f64,f32-guo",
                     help="storage formats; storage-guo runs the GS-WBS with Guo forcing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
