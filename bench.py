@@ -178,6 +178,8 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
     for k in range(len(arrivals)):
         e = int(g.integers(48, 193))
         reqs.append((inputs.porous_domain(e, seed + 1 + k), int(g.integers(2000, 20001))))
+        if (k + 1) % 20 == 0:
+            print(f"# serving: generated {k + 1}/{len(arrivals)} requests", file=sys.stderr, flush=True)
     srv = lbm.Server(storage=storage, max_slots=64, steps_per_tick=steps_per_tick, max_cells=192 ** 3)
     t0 = time.perf_counter()
     tickets = []
@@ -188,7 +190,26 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
         tickets.append(srv.submit_workload(w, steps, conv_tol=1e-6))
         st = srv.stats()
         depth = max(depth, st["queued"] + st["active"])
-    res = [srv.wait(t, drain_s) for t in tickets]
+    # collect results, giving the queue drain_s after the last arrival to finish; a
+    # progress line every 15 s (a saturated queue can run for minutes)
+    res = [None] * len(tickets)
+    pending = list(range(len(tickets)))
+    deadline = time.perf_counter() + drain_s
+    last = time.perf_counter()
+    while pending and time.perf_counter() < deadline:
+        r = srv.wait(tickets[pending[0]], 1.0)
+        if r is not None:
+            res[pending.pop(0)] = r
+        for k in list(pending):
+            r = srv.poll(tickets[k])
+            if r is not None:
+                res[k] = r
+                pending.remove(k)
+        if time.perf_counter() - last > 15.0:
+            st = srv.stats()
+            print(f"# serving: {len(tickets) - len(pending)}/{len(tickets)} done, {st['active']} active, "
+                  f"{st['queued']} queued", file=sys.stderr, flush=True)
+            last = time.perf_counter()
     st = srv.stats()
     srv.close()
     done = [r for r in res if r is not None and r["status"] == 0]
@@ -266,6 +287,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=0.25, help="arrivals per second (0: no serving run)")
     ap.add_argument("--serve-seconds", type=float, default=40.0)
+    ap.add_argument("--serve-drain", type=float, default=120.0,
+                    help="seconds after the last arrival for the queue to finish")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (counter calibration)")
     args = ap.parse_args()
@@ -330,7 +353,7 @@ def main():
         line["ensemble"] = ensemble()
         print(f"# ensemble: {line['ensemble']}", file=sys.stderr, flush=True)
     if args.serve_rate > 0:
-        line["serving"] = serving(args.serve_rate, args.serve_seconds)
+        line["serving"] = serving(args.serve_rate, args.serve_seconds, drain_s=args.serve_drain)
         print(f"# serving: {line['serving']}", file=sys.stderr, flush=True)
     copy = stream_copy_gbs()
     line["stream_copy_GBs"] = round(copy, 1)
