@@ -49,9 +49,13 @@ class BatchRunner {
         int dev = 0, cus = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const int threads = ncomp * tile_x * tile_y;
-        grid_ = std::max(8, cus * (threads >= 1024 ? 2 : 4));
+        // every block resident from the start: blocks stride over the tiles in
+        // table order, so a block that had to wait for a CU would start its
+        // whole share late
+        grid_ = std::max(8, cus * hm::batch_blocks_per_cu(storage, ncomp, c_ns, tile_x, tile_y));
         cus_ = std::max(cus, 1);
+        tpc_ = std::max(1, hm_rt::env_int("LBM_BATCH_TILES_PER_CU", 2));
+        maxc_ = std::max(4, hm_rt::env_int("LBM_BATCH_MAX_CHUNK", 64));
         for (int j = 0; j < 2; ++j) {
             if (hipMalloc(&dev_[j], bytes_) != hipSuccess) return LBM_ENOMEM;
             if (hipHostMalloc(reinterpret_cast<void**>(&host_[j]), bytes_, hipHostMallocDefault) != hipSuccess)
@@ -94,12 +98,13 @@ class BatchRunner {
         const int j = slot_;
         slot_ ^= 1;
         HIP_TRY(hipEventSynchronize(copied_[j]));  // host copy j is free again
-        // z-chunks from the batch as a whole: about four tiles per CU, no
-        // tile longer than 32 planes (blocks stride over tiles of unequal
-        // domains, short tiles balance them), none shorter than 16 (each
-        // chunk re-reads two halo planes) unless the batch would then give
-        // fewer than two tiles per CU: a few small domains alone would leave
-        // most of the GPU idle, and the halo re-reads cost little there
+        // z-chunks from the batch as a whole: about tpc_ tiles per CU, none
+        // longer than maxc_ planes (blocks stride over tiles of unequal
+        // domains, shorter tiles balance them; longer tiles pay the pipeline
+        // fill of a tile less often), none shorter than 16 (each chunk
+        // re-reads two halo planes) unless the batch would then give fewer
+        // than two tiles per CU: a few small domains alone would leave most
+        // of the GPU idle, and the halo re-reads cost little there
         balanced_.assign(d, d + n);
         int64_t cols = 0, tiles16 = 0;
         for (const hm::BatchDomain& b : balanced_) {
@@ -108,12 +113,18 @@ class BatchRunner {
             tiles16 += c * ((b.prob.nz + 15) / 16);
         }
         const int64_t min_chunk = tiles16 >= 2 * static_cast<int64_t>(cus_) ? 16 : 4;
-        const int64_t per_cols = std::max<int64_t>(1, (4 * static_cast<int64_t>(cus_) + cols - 1) / std::max<int64_t>(cols, 1));
+        const int64_t per_cols =
+            std::max<int64_t>(1, (tpc_ * static_cast<int64_t>(cus_) + cols - 1) / std::max<int64_t>(cols, 1));
         for (hm::BatchDomain& b : balanced_) {
-            const int64_t chunks = std::max<int64_t>(per_cols, (b.prob.nz + 31) / 32);
+            const int64_t chunks = std::max<int64_t>(per_cols, (b.prob.nz + maxc_ - 1) / maxc_);
             b.zchunk = static_cast<int>(
                 std::min<int64_t>(b.prob.nz, std::max<int64_t>(min_chunk, (b.prob.nz + chunks - 1) / chunks)));
         }
+        // longest tiles first: blocks take tiles in table order, so the
+        // short ones fill in at the end (longest-processing-time order)
+        std::stable_sort(balanced_.begin(), balanced_.end(), [](const hm::BatchDomain& a, const hm::BatchDomain& b) {
+            return a.zchunk > b.zchunk;
+        });
         hm::batch_encode(storage_, balanced_.data(), n, tx_, ty_, host_[j]);
         HIP_TRY(hipMemcpyAsync(dev_[j], host_[j], bytes_, hipMemcpyHostToDevice, stream_));
         HIP_TRY(hipEventRecord(copied_[j], stream_));
@@ -161,6 +172,7 @@ class BatchRunner {
 
   private:
     int storage_ = 0, ncomp_ = 0, c_ns_ = 0, tx_ = 64, ty_ = 8, kmax_ = 1, grid_ = 512, cus_ = 256;
+    int tpc_ = 2, maxc_ = 64;  // tiles per CU aimed at, longest z-chunk
     std::vector<hm::BatchDomain> balanced_;
     size_t bytes_ = 0;
     hipStream_t stream_ = nullptr;

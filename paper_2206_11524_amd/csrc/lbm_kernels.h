@@ -115,6 +115,10 @@ int batch_encode(int storage, const BatchDomain* d, int n, int tile_x, int tile_
 // Tile shapes compiled for the batched kernel.
 bool batch_tile_supported(int tile_x, int tile_y);
 
+// Blocks of the batched kernel that fit one CU at once (registers, LDS); at
+// least 1.
+int batch_blocks_per_cu(int storage, int ncomp, int c_ns, int tile_x, int tile_y);
+
 // Launch k of a tick: every domain with k < steps takes one step.  The grid
 // strides over all tiles of the table, so any fixed grid size works.
 hipError_t launch_step_batch(int storage, int ncomp, int c_ns, int tile_x, int tile_y, const void* table, int k,

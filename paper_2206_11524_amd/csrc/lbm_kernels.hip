@@ -991,7 +991,12 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step_batch(const char* __restric
     const BatchEntry<T>* ent = reinterpret_cast<const BatchEntry<T>*>(table + kBatchEntryOffset);
     const int total = hdr->total_tiles;
     const int nd = hdr->ndom;
-    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    // XCD-aware order, as in k_step: blocks are dispatched round-robin over
+    // the 8 XCDs, so give each XCD a contiguous run of every stride of tiles
+    // (neighbouring tiles re-read each other's edge cells through its L2)
+    const int nb = gridDim.x;
+    const int b0 = (nb & 7) == 0 ? (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    for (int w = b0; w < total; w += nb) {
         int lo = 0, hi = nd - 1;  // last domain with tile_begin <= w
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -1484,6 +1489,43 @@ static hipError_t batch_st(int ncomp, int c_ns, int tx, int ty, const void* tabl
 }
 
 bool batch_tile_supported(int tx, int ty) { return (tx == 64 && ty == 8) || (tx == 32 && ty == 8); }
+
+template <typename ST, int NC, int CNS, int TX, int TY>
+static int batch_occ_t()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<ST, NC, CNS, TX, TY>, NC * TX * TY, 0) !=
+        hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+template <typename ST, int NC, int CNS>
+static int batch_occ_tile(int tx, int ty)
+{
+    if (tx == 64 && ty == 8) return batch_occ_t<ST, NC, CNS, 64, 8>();
+    if (tx == 32 && ty == 8) return batch_occ_t<ST, NC, CNS, 32, 8>();
+    return 1;
+}
+
+template <typename ST>
+static int batch_occ_st(int ncomp, int c_ns, int tx, int ty)
+{
+    if (ncomp == 1) return batch_occ_tile<ST, 1, 1>(tx, ty);
+    if (c_ns == 1) return batch_occ_tile<ST, 2, 1>(tx, ty);
+    return batch_occ_tile<ST, 2, 2>(tx, ty);
+}
+
+int batch_blocks_per_cu(int storage, int ncomp, int c_ns, int tile_x, int tile_y)
+{
+    switch (storage) {
+    case kF64: return batch_occ_st<F64>(ncomp, c_ns, tile_x, tile_y);
+    case kF32: return batch_occ_st<F32>(ncomp, c_ns, tile_x, tile_y);
+    case kF16: return batch_occ_st<F16>(ncomp, c_ns, tile_x, tile_y);
+    case kBF16: return batch_occ_st<BF16>(ncomp, c_ns, tile_x, tile_y);
+    default: return 1;
+    }
+}
 
 hipError_t launch_step_batch(int storage, int ncomp, int c_ns, int tile_x, int tile_y, const void* table, int k,
                              int grid, hipStream_t st)
