@@ -162,7 +162,7 @@ def ensemble(storage="f16s", ndom=64, steps=100, warmup=10, seed=3000):
             "edges": {int(e): int((edges == e).sum()) for e in sorted(set(edges.tolist()))}}
 
 
-def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0):
+def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0, tile_x=64):
     """Continuous-batching serving: Poisson arrivals at `rate` per second for
     `seconds`, each a porous domain of edge U{48..192} asking for U{2000..20000}
     steps or convergence to 1e-6 relative momentum change; reports completion
@@ -180,7 +180,8 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
         reqs.append((inputs.porous_domain(e, seed + 1 + k), int(g.integers(2000, 20001))))
         if (k + 1) % 20 == 0:
             print(f"# serving: generated {k + 1}/{len(arrivals)} requests", file=sys.stderr, flush=True)
-    srv = lbm.Server(storage=storage, max_slots=64, steps_per_tick=steps_per_tick, max_cells=192 ** 3)
+    srv = lbm.Server(storage=storage, max_slots=64, steps_per_tick=steps_per_tick, max_cells=192 ** 3,
+                     tile=(tile_x, 8))
     t0 = time.perf_counter()
     tickets = []
     depth = 0
@@ -289,6 +290,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=40.0)
     ap.add_argument("--serve-drain", type=float, default=120.0,
                     help="seconds after the last arrival for the queue to finish")
+    ap.add_argument("--serve-tile", type=int, default=64, choices=(32, 64),
+                    help="tile width of the batched kernel in the server")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (counter calibration)")
     args = ap.parse_args()
@@ -353,7 +356,8 @@ def main():
         line["ensemble"] = ensemble()
         print(f"# ensemble: {line['ensemble']}", file=sys.stderr, flush=True)
     if args.serve_rate > 0:
-        line["serving"] = serving(args.serve_rate, args.serve_seconds, drain_s=args.serve_drain)
+        line["serving"] = serving(args.serve_rate, args.serve_seconds, drain_s=args.serve_drain,
+                                  tile_x=args.serve_tile)
         print(f"# serving: {line['serving']}", file=sys.stderr, flush=True)
     copy = stream_copy_gbs()
     line["stream_copy_GBs"] = round(copy, 1)
