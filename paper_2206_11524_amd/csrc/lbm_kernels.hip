@@ -601,7 +601,7 @@ struct TileShared {
     // (private to each thread) until it is collided, which frees the
     // registers that keep the next plane's loads in flight
     static constexpr size_t kBase = sizeof(T) * (4 * NC * LP + 3 * NC * 3 * NTC) + sizeof(float) * 4 * CNS * LP;
-    static constexpr bool kPipe = sizeof(T) == 4 && kBase + sizeof(T) * kQ * NT <= 160 * 1024;
+    static constexpr bool kPipe = kBase + sizeof(T) * kQ * NT <= 160 * 1024;
     T rho[4][NC][LP];
     float ns[4][CNS][LP];
     T j[3][NC][3][NTC];
