@@ -597,9 +597,10 @@ struct TileShared {
     static constexpr int LP = LW * (TY + 2);
     static constexpr int NTC = TX * TY;
     static constexpr int NT = NC * NTC;
-    // FP32 arithmetic: the populations of the plane staged last wait here
-    // (private to each thread) until it is collided, which frees the
-    // registers that keep the next plane's loads in flight
+    // Where the tile fits the 160 KB of LDS with it: the populations of the
+    // plane staged last wait here (private to each thread) until it is
+    // collided, which frees the registers that keep the next plane's loads
+    // in flight (the three-plane sweep of step_tile)
     static constexpr size_t kBase = sizeof(T) * (4 * NC * LP + 3 * NC * 3 * NTC) + sizeof(float) * 4 * CNS * LP;
     static constexpr bool kPipe = kBase + sizeof(T) * kQ * NT <= 160 * 1024;
     T rho[4][NC][LP];
