@@ -85,3 +85,36 @@ def test_one_step_at_full_size(electrode, storage, forcing):
     worst = np.unravel_index(np.argmax(excess), excess.shape)
     assert excess.max() <= 0.0, (storage, len(cells), float(excess.max()), int(cells[worst[0]]), worst)
     assert np.isfinite(f_t1).all()
+
+
+def test_one_step_beyond_two_gib_per_component():
+    """320^3 in FP32: the 19 direction arrays of one component span 2.49 GB,
+    beyond 2^31 bytes, so the kernel's 32-bit buffer offsets go past the sign
+    bit (and the offset that parks lanes without a ring cell may land inside
+    the buffer: a wasted load there, never a wrong value).  One step, sampled
+    cells, against the oracle, to the same bound as above."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    _, w19, _ = oracle.lattice(19)
+    w = inputs.electrode(320)
+    assert 19 * w.ncells * 4 > 2 ** 31
+    sim = lbm.from_workload(w, storage="f32")
+    sim.step(2)
+    f_t = sim.populations()
+    sim.step(1)
+    f_t1 = sim.populations()
+    rho0 = np.array(lbm.default_shift("f32", 2, w.rho))[:2]
+    sim.close()
+    nx, ny, nz = w.shape
+    g = np.random.Generator(np.random.PCG64(11))
+    p = np.concatenate([g.integers(0, [nx, ny, nz], size=(800, 3)),
+                        np.stack([g.integers(0, nx, 400), g.integers(0, ny, 400), g.choice([nz - 1, nz - 2, 0, 1], 400)], 1)])
+    cells = np.unique((p[:, 2].astype(np.int64) * ny + p[:, 1]) * nx + p[:, 0])
+    ref = oracle_for(w).cell_update(f_t, cells)
+    got = f_t1.reshape(2, 19, -1)[:, :, cells].transpose(2, 0, 1)
+    h_ref = ref - w19[None, None, :] * rho0[None, :, None]
+    bound = _U["f32"] * np.abs(h_ref) + 2e-6 * np.abs(ref).max()
+    assert (np.abs(got - ref) - bound).max() <= 0.0
+    assert np.isfinite(f_t1).all()
