@@ -162,11 +162,13 @@ def ensemble(storage="f16s", ndom=64, steps=100, warmup=10, seed=3000):
             "edges": {int(e): int((edges == e).sum()) for e in sorted(set(edges.tolist()))}}
 
 
-def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0, tile_x=64):
+def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0, tile_x=64,
+            policy="fair", run_cells=0):
     """Continuous-batching serving: Poisson arrivals at `rate` per second for
     `seconds`, each a porous domain of edge U{48..192} asking for U{2000..20000}
     steps or convergence to 1e-6 relative momentum change; reports completion
-    latency percentiles and the aggregate MLUPS of the server."""
+    latency percentiles and the aggregate MLUPS of the server under the given
+    sharing policy ("fair" or "shortest-first")."""
     from paper_2206_11524_amd import inputs, lbm
 
     g = np.random.Generator(np.random.PCG64(seed))
@@ -181,7 +183,8 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
         if (k + 1) % 20 == 0:
             print(f"# serving: generated {k + 1}/{len(arrivals)} requests", file=sys.stderr, flush=True)
     srv = lbm.Server(storage=storage, max_slots=64, steps_per_tick=steps_per_tick, max_cells=192 ** 3,
-                     tile=(tile_x, 8))
+                     tile=(tile_x, 8), policy=policy,
+                     run_cells=run_cells)
     t0 = time.perf_counter()
     tickets = []
     depth = 0
@@ -216,7 +219,8 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
     done = [r for r in res if r is not None and r["status"] == 0]
     lat = np.array([r["t_done"] - r["t_submit"] for r in done])
     return {"rate_per_s": rate, "arrival_window_s": seconds, "requests": len(reqs), "completed": len(done),
-            "converged": int(sum(r["converged"] for r in done)), "storage": storage,
+            "converged": int(sum(r["converged"] for r in done)), "storage": storage, "policy": policy,
+            "mean_latency_s": round(float(lat.mean()), 3) if len(lat) else None,
             "p50_latency_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
             "p99_latency_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
             "aggregate_mlups": round(st["cell_updates"] / max(st["busy_seconds"], 1e-9) / 1e6, 1),
@@ -290,6 +294,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=40.0)
     ap.add_argument("--serve-drain", type=float, default=120.0,
                     help="seconds after the last arrival for the queue to finish")
+    ap.add_argument("--serve-policy", default="fair", choices=("fair", "shortest-first"),
+                    help="how the server shares each tick among resident requests")
+    ap.add_argument("--serve-run-cells", type=int, default=0,
+                    help="shortest-first: cells stepped per tick at least (0: the library default)")
     ap.add_argument("--serve-tile", type=int, default=64, choices=(32, 64),
                     help="tile width of the batched kernel in the server")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -357,7 +365,8 @@ def main():
         print(f"# ensemble: {line['ensemble']}", file=sys.stderr, flush=True)
     if args.serve_rate > 0:
         line["serving"] = serving(args.serve_rate, args.serve_seconds, drain_s=args.serve_drain,
-                                  tile_x=args.serve_tile)
+                                  tile_x=args.serve_tile, policy=args.serve_policy,
+                                  run_cells=args.serve_run_cells)
         print(f"# serving: {line['serving']}", file=sys.stderr, flush=True)
     copy = stream_copy_gbs()
     line["stream_copy_GBs"] = round(copy, 1)

@@ -276,12 +276,26 @@ void lbm_group_destroy(lbm_group* g);
  * densities, parameters, step budget, convergence tolerance) are queued by
  * lbm_batch_submit from any thread.  Each tick the worker admits queued
  * requests while a slot is free and the resident state fits the HBM budget,
- * replays a captured graph of steps_per_tick batched launches over all
- * resident domains (a domain that needs fewer steps stops early), checks the
- * FP64 momentum of each domain, and retires those that reached their step
+ * replays a captured graph of steps_per_tick batched launches over the
+ * resident domains its policy steps (a domain that needs fewer steps stops
+ * early), checks the FP64 momentum of each domain it stepped, and retires
+ * those that reached their step
  * budget or converged.  Each result is the same as running the request alone.
  */
 typedef struct lbm_server lbm_server;
+
+/* How a tick's launches are shared among the resident domains.  FAIR steps
+ * every resident domain each tick (processor sharing).  SHORTEST_FIRST steps
+ * only the domains with the least remaining work, cells x (max_steps -
+ * steps_done), smallest first, until the stepped set holds run_cells cells;
+ * the others wait with their state untouched.  It lowers mean completion time
+ * when short and long requests mix; a long request waits while shorter ones
+ * keep arriving and fill run_cells, and the convergence test of a request
+ * runs only on the ticks that step it. */
+typedef enum {
+    LBM_SERVE_FAIR = 0,
+    LBM_SERVE_SHORTEST_FIRST = 1
+} lbm_serve_policy;
 
 typedef struct {
     uint64_t hbm_budget_bytes; /* resident population + n_s bytes; 0: 90 % of free device memory */
@@ -291,6 +305,9 @@ typedef struct {
     int32_t ncomp, c_ns;       /* component and n_s-field counts of every request            */
     int64_t max_cells;         /* largest accepted domain (sizes the shared scratch)         */
     int32_t tile_x, tile_y;    /* tile of the batched kernel; 0: 64 x 8                      */
+    int32_t policy;            /* lbm_serve_policy                                           */
+    int32_t pad;               /* must be 0                                                  */
+    int64_t run_cells;         /* SHORTEST_FIRST: cells stepped per tick at least; 0: 2^24   */
 } lbm_server_cfg;
 
 typedef struct {

@@ -458,13 +458,30 @@ void lbm_server::run()
             st.active = static_cast<int64_t>(active.size());
             st.bytes_resident = resident;
         }
-        // one tick: K launches over every resident domain
+        // one tick: K launches over the resident domains this tick steps
         const int K = runner.kmax();
+        std::vector<int> steps(active.size());
+        for (size_t i = 0; i < active.size(); ++i)
+            steps[i] = static_cast<int>(std::min<int64_t>(K, active[i].req.max_steps - active[i].steps_done));
+        if (cfg.policy == LBM_SERVE_SHORTEST_FIRST) {
+            std::vector<size_t> order(active.size());
+            std::vector<double> work(active.size());
+            for (size_t i = 0; i < active.size(); ++i) {
+                order[i] = i;
+                work[i] = static_cast<double>(active[i].ctx->prob.N) *
+                          static_cast<double>(active[i].req.max_steps - active[i].steps_done);
+            }
+            std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work[a] < work[b]; });
+            int64_t stepped = 0;
+            for (size_t i : order) {
+                if (stepped >= cfg.run_cells) steps[i] = 0;
+                else stepped += active[i].ctx->prob.N;
+            }
+        }
         doms.clear();
         double cells = 0.0;
-        std::vector<int> steps(active.size());
         for (size_t i = 0; i < active.size(); ++i) {
-            steps[i] = static_cast<int>(std::min<int64_t>(K, active[i].req.max_steps - active[i].steps_done));
+            if (!steps[i]) continue;
             doms.push_back(domain_of(active[i].ctx, steps[i]));
             cells += static_cast<double>(active[i].ctx->prob.N) * steps[i];
         }
@@ -490,7 +507,7 @@ void lbm_server::run()
                 retire(i, LBM_OK, false);
                 continue;
             }
-            if (sl.req.tol > 0.0) {
+            if (sl.req.tol > 0.0 && steps[i] > 0) {
                 lbm_totals tt{};
                 const int trc = lbm_totals_get(sl.ctx, &tt);
                 if (trc || !tt.finite) {
@@ -524,6 +541,9 @@ int lbm_server_create(const lbm_server_cfg* cfg, void* reserved, lbm_server** ou
     if (cfg->storage < LBM_F64 || cfg->storage > LBM_BF16S) return LBM_EINVAL;
     if (cfg->ncomp < 1 || cfg->ncomp > 2 || cfg->c_ns < 1 || cfg->c_ns > cfg->ncomp) return LBM_EINVAL;
     if (cfg->max_cells >= (int64_t(1) << 31)) return LBM_EINVAL;
+    if (cfg->policy < LBM_SERVE_FAIR || cfg->policy > LBM_SERVE_SHORTEST_FIRST || cfg->pad != 0 ||
+        cfg->run_cells < 0)
+        return LBM_EINVAL;
     const int tx = cfg->tile_x ? cfg->tile_x : 64, ty = cfg->tile_y ? cfg->tile_y : 8;
     if (!hm::batch_tile_supported(tx, ty)) return LBM_EINVAL;
     lbm_server* s = new (std::nothrow) lbm_server();
@@ -531,6 +551,7 @@ int lbm_server_create(const lbm_server_cfg* cfg, void* reserved, lbm_server** ou
     s->cfg = *cfg;
     s->cfg.tile_x = tx;
     s->cfg.tile_y = ty;
+    if (!s->cfg.run_cells) s->cfg.run_cells = int64_t(1) << 24;
     s->t0 = std::chrono::steady_clock::now();
     if (hipGetDevice(&s->device) != hipSuccess || hipStreamCreate(&s->stream) != hipSuccess) {
         delete s;

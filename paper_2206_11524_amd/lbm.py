@@ -306,7 +306,11 @@ def from_workload(w, storage="f32", rho_shift=None, store_scale_log2=0, check_ev
 class ServerCfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int32), ("steps_per_tick", C.c_int32),
                 ("storage", C.c_int32), ("ncomp", C.c_int32), ("c_ns", C.c_int32), ("max_cells", C.c_int64),
-                ("tile_x", C.c_int32), ("tile_y", C.c_int32)]
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("policy", C.c_int32), ("pad", C.c_int32),
+                ("run_cells", C.c_int64)]
+
+
+SERVE_POLICY = {"fair": 0, "shortest-first": 1}
 
 
 class Request(C.Structure):
@@ -383,11 +387,12 @@ class Server:
     """Continuous-batching server (worker thread inside the library)."""
 
     def __init__(self, storage="f16s", ncomp=2, c_ns=1, max_slots=64, steps_per_tick=100, max_cells=192 ** 3,
-                 hbm_budget_bytes=0, tile=(64, 8)):
+                 hbm_budget_bytes=0, tile=(64, 8), policy="fair", run_cells=0):
         self.lib = _serve_lib()
         cfg = ServerCfg(int(hbm_budget_bytes), int(max_slots), int(steps_per_tick),
                         STORAGE[storage] if isinstance(storage, str) else int(storage), ncomp, c_ns,
-                        int(max_cells), tile[0], tile[1])
+                        int(max_cells), tile[0], tile[1],
+                        SERVE_POLICY[policy] if isinstance(policy, str) else int(policy), 0, int(run_cells))
         s = C.c_void_p()
         _check(self.lib.lbm_server_create(C.byref(cfg), None, C.byref(s)), "lbm_server_create")
         self.s = s

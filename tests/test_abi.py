@@ -87,6 +87,17 @@ def test_invalid_forcing_scheme_rejected(lib):
     assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_EINVAL
 
 
+@pytest.mark.parametrize("field,value", [("policy", 2), ("policy", -1), ("pad", 1), ("run_cells", -5)])
+def test_invalid_server_config_rejected(lib, field, value):
+    """Rejected before the library touches a device (so this runs without one)."""
+    lbm._serve_lib()
+    cfg = lbm.ServerCfg(0, 4, 10, lbm.STORAGE["f32"], 2, 1, 32 ** 3, 64, 8, 0, 0, 0)
+    setattr(cfg, field, value)
+    s = C.c_void_p()
+    assert lib.lbm_server_create(C.byref(cfg), None, C.byref(s)) == lbm.LBM_EINVAL
+    assert not s.value
+
+
 _STRUCTS = ["lbm_domain", "lbm_reservoir", "lbm_params", "lbm_sizes", "lbm_device_buffers", "lbm_totals",
             "lbm_fill_query", "lbm_fill_state", "lbm_server_cfg", "lbm_request", "lbm_result", "lbm_server_stats"]
 

@@ -7,7 +7,8 @@
 * The server: every request's result (final densities, FP64 totals) is bit for
   bit the result of running that request alone for the same number of steps,
   whatever else shared the GPU; admission respects the HBM budget; errors are
-  reported per request.
+  reported per request; the shortest-first policy keeps those results and
+  finishes short requests before long ones.
 """
 import time
 
@@ -167,3 +168,34 @@ def test_server_many_small_requests_complete():
     assert all(r is not None and r["status"] == 0 for r in out)
     assert st["completed"] == 40 and st["cell_updates"] > 0
     assert time.time() - t0 < 120
+
+
+@pytest.mark.parametrize("run_cells", [1, 32 ** 3])
+def test_server_shortest_first_keeps_results_and_order(run_cells):
+    storage = "f32"
+    # run_cells = 1: each tick steps only the request with the least remaining
+    # work; 32^3: the few least, until they hold that many cells; the rest wait
+    # untouched
+    srv = lbm.Server(storage=storage, max_slots=8, steps_per_tick=20, max_cells=40 ** 3,
+                     policy="shortest-first", run_cells=run_cells)
+    ws = [inputs.porous_domain(e, 7000 + k) for k, e in enumerate([40, 24, 32, 40, 16])]
+    steps = [200, 60, 100, 40, 300]
+    tickets = [srv.submit_workload(w, s, want_rho=True) for w, s in zip(ws, steps)]
+    res = [srv.wait(t, 120.0) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(ws)
+    for w, n, r in zip(ws, steps, res):
+        assert r is not None and r["status"] == 0 and r["steps_done"] == n
+        sim = lbm.from_workload(w, storage=storage)
+        sim.step(n)
+        m = sim.moments()
+        sim.close()
+        assert np.array_equal(r["rho"], m["rho"])
+    if run_cells > 1:
+        return
+    # one request at a time: completion follows the work (cells x steps) when
+    # all arrive at once
+    work = [w.ncells * n for w, n in zip(ws, steps)]
+    done = [r["t_done"] for r in res]
+    assert sorted(range(len(ws)), key=lambda k: done[k]) == sorted(range(len(ws)), key=lambda k: work[k])
