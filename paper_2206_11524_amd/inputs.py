@@ -22,6 +22,7 @@ available, these synthetic stand-ins have the same structure):
 * ``electrode``      random overlapping spheres + smoothed gray binder + reservoirs
                      (electrolyte filling, Sec. 4)
 * ``porous_domain``  random-sphere packing with a smoothed gray field (ensembles)
+* ``washburn_channel`` imbibition into a uniform gray medium (Sec. 3.4)
 """
 from __future__ import annotations
 
@@ -244,3 +245,24 @@ def porous_domain(edge, seed, porosity=None, ns_max=0.9, G=0.9, G_ads=(0.1, -0.1
     r[1, :quarter][~solid[:quarter]] = rho_dis
     return Workload((n, n, n), ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads), g_scale=3.0,
                     F_ext=(0.0, 0.0, force), name=f"porous{n}_{seed}")
+
+
+def washburn_channel(G_ads, ns_medium, H=500, L=2, res_width=4, gap=8, rho_main=0.99, rho_dis=0.01) -> Workload:
+    """Imbibition channel of Sec. 3.4, one cell deep in z (the paper's 2-D
+    set-up; periodic in y, where the state stays uniform, so L only sets the
+    tile shape): a fluid-1 reservoir at x < res_width, a free gap of `gap`
+    cells, then a homogenized medium of uniform n_s up to the fluid-2
+    reservoir at x >= H - res_width; fluid 2 fills the rest at the start.
+    Table 1 fluids (0.99 / 0.01, tau = 1), G_inter,12 = 1.75 and
+    G_ads,2 = -G_ads,1 = G_ads: fluid 1 wets the medium for G_ads > 0.  The
+    paper does not state how its inlet meets the medium; the n_s step at the
+    end of the gap is what drives the front here."""
+    x0 = res_width + gap
+    ns = np.zeros((1, 1, L, H), np.float32)
+    ns[..., x0:H - res_width] = ns_medium
+    r = np.empty((2, 1, L, H))
+    r[0], r[1] = rho_dis, rho_main
+    r[0, ..., :res_width], r[1, ..., :res_width] = rho_main, rho_dis
+    res = [(0, 0, res_width, (rho_main, rho_dis)), (0, H - res_width, H, (rho_dis, rho_main))]
+    return Workload((H, L, 1), ns, r, ncomp=2, tau=(1.0, 1.0), G=1.75, G_ads=(-G_ads, G_ads), g_scale=1.0,
+                    reservoirs=res, name=f"washburn{H}_{G_ads}_{ns_medium}")

@@ -17,3 +17,17 @@ def rel_max_err(a, b):
     """max |a - b| / max |b| (field max-norm relative error)."""
     den = np.abs(b).max()
     return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def front_position(rho, x0, tail=5):
+    """Washburn front (Sec. 3.4): the last x >= x0 where rho_1 - rho_2,
+    averaged over y and z, changes sign from positive to negative, refined by
+    linear interpolation, measured from x0; None before the front reaches x0.
+    rho is [2, nz, ny, nx]; the last `tail` cells (outlet reservoir) are left out."""
+    r = rho.mean(axis=(1, 2))
+    phi = r[0] - r[1]
+    idx = np.nonzero((phi[x0:-tail] > 0) & (phi[x0 + 1:-tail + 1] <= 0))[0]
+    if not len(idx):
+        return None
+    i = idx[-1] + x0
+    return i + phi[i] / (phi[i] - phi[i + 1]) - x0
