@@ -188,11 +188,22 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
     t0 = time.perf_counter()
     tickets = []
     depth = 0
+    trace = []  # (seconds since the first arrival, queued, resident), about once a second
+
+    def sample(force=False):
+        now = time.perf_counter() - t0
+        if not (force or not trace or now - trace[-1][0] >= 1.0):
+            return None
+        st = srv.stats()
+        trace.append((round(now, 1), st["queued"], st["active"]))
+        return st
+
     for (w, steps), ta in zip(reqs, arrivals):
         while time.perf_counter() - t0 < ta:
+            sample()
             time.sleep(0.002)
         tickets.append(srv.submit_workload(w, steps, conv_tol=1e-6))
-        st = srv.stats()
+        st = sample(force=True)
         depth = max(depth, st["queued"] + st["active"])
     # collect results, giving the queue drain_s after the last arrival to finish; a
     # progress line every 15 s (a saturated queue can run for minutes)
@@ -209,6 +220,7 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
             if r is not None:
                 res[k] = r
                 pending.remove(k)
+        sample()
         if time.perf_counter() - last > 15.0:
             st = srv.stats()
             print(f"# serving: {len(tickets) - len(pending)}/{len(tickets)} done, {st['active']} active, "
@@ -224,7 +236,8 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
             "p50_latency_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
             "p99_latency_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
             "aggregate_mlups": round(st["cell_updates"] / max(st["busy_seconds"], 1e-9) / 1e6, 1),
-            "max_in_system": depth, "ticks": st["ticks"]}
+            "max_in_system": depth, "ticks": st["ticks"],
+            "depth_trace": {"columns": ["t_s", "queued", "resident"], "rows": trace}}
 
 
 def cpu_baseline(w, budget_s=20.0):
