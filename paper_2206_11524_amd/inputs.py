@@ -23,6 +23,7 @@ available, these synthetic stand-ins have the same structure):
                      (electrolyte filling, Sec. 4)
 * ``porous_domain``  random-sphere packing with a smoothed gray field (ensembles)
 * ``washburn_channel`` imbibition into a uniform gray medium (Sec. 3.4)
+* ``obstacle_channel`` two-phase flow past porous obstacles (Sec. 3.5)
 """
 from __future__ import annotations
 
@@ -266,3 +267,27 @@ def washburn_channel(G_ads, ns_medium, H=500, L=2, res_width=4, gap=8, rho_main=
     res = [(0, 0, res_width, (rho_main, rho_dis)), (0, H - res_width, H, (rho_dis, rho_main))]
     return Workload((H, L, 1), ns, r, ncomp=2, tau=(1.0, 1.0), G=1.75, G_ads=(-G_ads, G_ads), g_scale=1.0,
                     reservoirs=res, name=f"washburn{H}_{G_ads}_{ns_medium}")
+
+
+def obstacle_channel(ns1, L=300, H=50, radius=16.5, spacing=60, first=30.0, res_width=4, force=5e-5,
+                     rho_main=0.99, rho_dis=0.01) -> Workload:
+    """Porous-obstacle channel of Sec. 3.5, one cell deep in z: five discs of
+    radius 16.5 on the channel axis y = (H - 1)/2, centres `spacing` apart
+    from x = `first` (the paper gives diameter and spacing, not the offset),
+    periodic in y.  Two n_s fields: n_s,1 = ns1 inside the discs and 0
+    elsewhere, n_s,2 = 0 everywhere.  Fluid-1 reservoir at x < res_width,
+    fluid-2 reservoir at x >= L - res_width, fluid 2 elsewhere at the start;
+    body force `force` along +x on both fluids; Table 1 fluids, G_inter =
+    1.75, no adhesion (the paper states no contact angle here)."""
+    y, x = np.meshgrid(np.arange(H), np.arange(L), indexing="ij")
+    inside = np.zeros((H, L), bool)
+    for k in range(5):
+        inside |= (x - (first + spacing * k)) ** 2 + (y - (H - 1) / 2) ** 2 <= radius * radius
+    ns = np.zeros((2, 1, H, L), np.float32)
+    ns[0, 0][inside] = ns1
+    r = np.empty((2, 1, H, L))
+    r[0], r[1] = rho_dis, rho_main
+    r[0, ..., :res_width], r[1, ..., :res_width] = rho_main, rho_dis
+    res = [(0, 0, res_width, (rho_main, rho_dis)), (0, L - res_width, L, (rho_dis, rho_main))]
+    return Workload((L, H, 1), ns, r, ncomp=2, tau=(1.0, 1.0), G=1.75, G_ads=(0.0, 0.0), F_ext=(force, 0.0, 0.0),
+                    g_scale=1.0, reservoirs=res, name=f"obstacles{L}x{H}_{ns1}")
