@@ -31,3 +31,21 @@ def front_position(rho, x0, tail=5):
         return None
     i = idx[-1] + x0
     return i + phi[i] / (phi[i] - phi[i + 1]) - x0
+
+
+def build_c_driver(out):
+    """Compile tests/c_driver/abi_driver.c against include/lbm.h and link it to
+    the built library (gcc only; no Python or PyTorch in the program)."""
+    import os
+    import subprocess
+
+    from paper_2206_11524_amd import lbm
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.dirname(lbm.LIB_PATH)
+    cmd = ["gcc", "-std=c11", "-O1", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(root, "include"),
+           os.path.join(root, "tests", "c_driver", "abi_driver.c"), "-L", pkg, "-lhmcsc", f"-Wl,-rpath,{pkg}",
+           "-Wl,-rpath-link,/opt/rocm/lib", "-lm", "-o", str(out)]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return out
+

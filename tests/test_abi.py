@@ -10,6 +10,8 @@ import pytest
 
 from paper_2206_11524_amd import lbm
 
+from _common import build_c_driver
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -176,3 +178,7 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.lbm_sync(None) == lbm.LBM_EINVAL
     assert lib.lbm_time(None) == -1
     lib.lbm_destroy(None)
+
+
+def test_c_program_compiles_and_links_against_the_header(lib, tmp_path):
+    assert os.path.exists(build_c_driver(tmp_path / "abi_driver"))
