@@ -835,8 +835,6 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
         // duplicate cell 0 of the staging list.
         constexpr int NT_ = TileShared<ST, NC, CNS, TX, TY>::NT;
         constexpr uint32_t kOff = 0x80000000u;  // beyond any buffer of a single component below 2 GiB
-        E rr[kQ];  // own populations of the next plane to stage, raw
-        E er[kQ];  // ring populations of the plane being staged, raw
         T* hs = &sh.hs[0][0] + threadIdx.x;
         PlaneOffs qr = qring;
         if (!ring)
@@ -858,65 +856,164 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                                     static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};
             pull_raw<ST>(ra, dir_bytes, so, q, e);
         };
-        // Stage plane p, whose own loads are in rr: ring loads and n_s are
-        // issued first; the own values give the density and first moments
-        // and go to hs, whose previous content (the plane before) moves to
-        // hz; then the own loads of plane pn are issued, and only after them
-        // the ring values are consumed, so a wait for the ring does not wait
-        // for plane pn.
-        auto stage_pipe = [&](int p, int slot, int js, int pn, T hz[kQ]) {
-            if constexpr (NC == 2) issue(p, qr, er);
-            const float* nsp = ns + static_cast<size_t>(p) * plane;
-            float nsv[NSMAX][CNS];
-#pragma unroll
-            for (int k = 0; k < NSMAX; ++k)
-#pragma unroll
-                for (int c = 0; c < CNS; ++c) nsv[k][c] = nsp[static_cast<size_t>(c) * a.N + no[k]];
-            __builtin_amdgcn_sched_barrier(0);
-            {
-                T h[kQ];
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) h[i] = ST::dec(rr[i], a.inv_scale);
-                reservoir_override(x, y, p, h);
-                s_rho[slot][s][me] = a.rho0[s] + sum19(h);
-                if (NC == 2 && js >= 0) {
-                    s_j[js][s][0][tj] = first_moment<T, 0>(h);
-                    s_j[js][s][1][tj] = first_moment<T, 1>(h);
-                    s_j[js][s][2][tj] = first_moment<T, 2>(h);
+        if constexpr (sizeof(E) != 2) {
+            E rr[kQ];  // own populations of the next plane to stage, raw
+            E er[kQ];  // ring populations of the plane being staged, raw
+            // Stage plane p, whose own loads are in rr: ring loads and n_s are
+            // issued first; the own values give the density and first moments
+            // and go to hs, whose previous content (the plane before) moves to
+            // hz; then the own loads of plane pn are issued, and only after them
+            // the ring values are consumed, so a wait for the ring does not wait
+            // for plane pn.
+            auto stage_pipe = [&](int p, int slot, int js, int pn, T hz[kQ]) {
+                if constexpr (NC == 2) issue(p, qr, er);
+                const float* nsp = ns + static_cast<size_t>(p) * plane;
+                float nsv[NSMAX][CNS];
+    #pragma unroll
+                for (int k = 0; k < NSMAX; ++k)
+    #pragma unroll
+                    for (int c = 0; c < CNS; ++c) nsv[k][c] = nsp[static_cast<size_t>(c) * a.N + no[k]];
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    T h[kQ];
+    #pragma unroll
+                    for (int i = 0; i < kQ; ++i) h[i] = ST::dec(rr[i], a.inv_scale);
+                    reservoir_override(x, y, p, h);
+                    s_rho[slot][s][me] = a.rho0[s] + sum19(h);
+                    if (NC == 2 && js >= 0) {
+                        s_j[js][s][0][tj] = first_moment<T, 0>(h);
+                        s_j[js][s][1][tj] = first_moment<T, 1>(h);
+                        s_j[js][s][2][tj] = first_moment<T, 2>(h);
+                    }
+    #pragma unroll
+                    for (int i = 0; i < kQ; ++i) {
+                        hz[i] = hs[i * NT_];
+                        hs[i * NT_] = h[i];
+                    }
                 }
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    hz[i] = hs[i * NT_];
-                    hs[i * NT_] = h[i];
+                __builtin_amdgcn_sched_barrier(0);
+                issue(pn, qme, rr);
+                __builtin_amdgcn_sched_barrier(0);
+                if (ring) {
+                    T hr[kQ];
+    #pragma unroll
+                    for (int i = 0; i < kQ; ++i) hr[i] = ST::dec(er[i], a.inv_scale);
+                    reservoir_override(rx, ry, p, hr);
+                    s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
                 }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            issue(pn, qme, rr);
-            __builtin_amdgcn_sched_barrier(0);
-            if (ring) {
-                T hr[kQ];
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) hr[i] = ST::dec(er[i], a.inv_scale);
-                reservoir_override(rx, ry, p, hr);
-                s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
-            }
-#pragma unroll
-            for (int k = 0; k < NSMAX; ++k)
-#pragma unroll
-                for (int c = 0; c < CNS; ++c) s_ns[slot][c][nl[k]] = nsv[k][c];
-        };
+    #pragma unroll
+                for (int k = 0; k < NSMAX; ++k)
+    #pragma unroll
+                    for (int c = 0; c < CNS; ++c) s_ns[slot][c][nl[k]] = nsv[k][c];
+            };
 
-        T hz[kQ];
-        // prologue: plane zs-1 (densities only), plane zs (to hs)
-        issue(wrapz(zs - 1), qme, rr);
-        stage_pipe(wrapz(zs - 1), rslot(zs - 1), -1, zs, hz);
-        stage_pipe(zs, rslot(zs), jslot(zs), wrapz(zs + 1), hz);
-        for (int z = zs; z < ze; ++z) {
-            // after the last plane the next loads repeat the one just staged (L2 hits)
-            const int pn = z + 2 <= ze ? wrapz(z + 2) : wrapz(z + 1);
-            stage_pipe(wrapz(z + 1), rslot(z + 1), jslot(z + 1), pn, hz);
-            __syncthreads();
-            collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hz, false);
+            T hz[kQ];
+            // prologue: plane zs-1 (densities only), plane zs (to hs)
+            issue(wrapz(zs - 1), qme, rr);
+            stage_pipe(wrapz(zs - 1), rslot(zs - 1), -1, zs, hz);
+            stage_pipe(zs, rslot(zs), jslot(zs), wrapz(zs + 1), hz);
+            for (int z = zs; z < ze; ++z) {
+                // after the last plane the next loads repeat the one just staged (L2 hits)
+                const int pn = z + 2 <= ze ? wrapz(z + 2) : wrapz(z + 1);
+                stage_pipe(wrapz(z + 1), rslot(z + 1), jslot(z + 1), pn, hz);
+                __syncthreads();
+                collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hz, false);
+            }
+        } else {
+            // 16-bit storage: two roles, fixed per wave (NTC is a multiple of
+            // 64, and the ring lanes are the first of each component).  Waves
+            // holding ring lanes stage the ring densities as well and keep one
+            // plane of own loads in flight; the others, free of the ring loads,
+            // keep two (a wave has at most 63 memory operations outstanding,
+            // and the 16-bit loads carry half the bytes each).  Both roles run
+            // the same loop with one barrier per plane.  Wider formats keep one
+            // role: there the deeper prefetch did not pay.
+            constexpr bool kDeep = true;
+            auto sweep = [&](auto ring_tag) {
+                constexpr bool RING = decltype(ring_tag)::value;
+                constexpr bool DEEP = kDeep && !RING;
+                constexpr int AHEAD = DEEP ? 2 : 1;  // planes between issue and consumption
+                E rA[kQ];
+                E rB[DEEP ? kQ : 1];
+                E er[RING ? kQ : 1];
+                // Stage plane p, whose own loads are in rc: (ring loads and) n_s
+                // are issued first; the own values give the density and first
+                // moments and go to hs, whose previous content (the plane before)
+                // moves to hz; then the own loads of plane pn are issued into rc,
+                // and only after them the ring values are consumed, so a wait for
+                // the ring does not wait for plane pn.
+                auto stage_pipe = [&](int p, int slot, int js, int pn, T hz[kQ], E rc[kQ]) {
+                    if constexpr (RING) issue(p, qr, er);
+                    const float* nsp = ns + static_cast<size_t>(p) * plane;
+                    float nsv[NSMAX][CNS];
+    #pragma unroll
+                    for (int k = 0; k < NSMAX; ++k)
+    #pragma unroll
+                        for (int c = 0; c < CNS; ++c) nsv[k][c] = nsp[static_cast<size_t>(c) * a.N + no[k]];
+                    __builtin_amdgcn_sched_barrier(0);
+                    {
+                        T h[kQ];
+    #pragma unroll
+                        for (int i = 0; i < kQ; ++i) h[i] = ST::dec(rc[i], a.inv_scale);
+                        reservoir_override(x, y, p, h);
+                        s_rho[slot][s][me] = a.rho0[s] + sum19(h);
+                        if (NC == 2 && js >= 0) {
+                            s_j[js][s][0][tj] = first_moment<T, 0>(h);
+                            s_j[js][s][1][tj] = first_moment<T, 1>(h);
+                            s_j[js][s][2][tj] = first_moment<T, 2>(h);
+                        }
+    #pragma unroll
+                        for (int i = 0; i < kQ; ++i) {
+                            hz[i] = hs[i * NT_];
+                            hs[i * NT_] = h[i];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    issue(pn, qme, rc);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if constexpr (RING) {
+                        if (ring) {
+                            T hr[kQ];
+    #pragma unroll
+                            for (int i = 0; i < kQ; ++i) hr[i] = ST::dec(er[i], a.inv_scale);
+                            reservoir_override(rx, ry, p, hr);
+                            s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
+                        }
+                    }
+    #pragma unroll
+                    for (int k = 0; k < NSMAX; ++k)
+    #pragma unroll
+                        for (int c = 0; c < CNS; ++c) s_ns[slot][c][nl[k]] = nsv[k][c];
+                };
+                // the plane whose loads a stage of plane p issues: p + AHEAD, or
+                // after the last plane one already staged again (L2 hits)
+                auto ahead = [&](int p) { return wrapz(p + AHEAD <= ze ? p + AHEAD : ze); };
+                // register sets: planes zs-1, zs+1, ... in r_odd, planes zs, zs+2, ...
+                // in r_even (one and the same set unless two planes are in flight)
+                E (&r_odd)[kQ] = rA;
+                E (&r_even)[kQ] = *reinterpret_cast<E(*)[kQ]>(DEEP ? static_cast<E*>(rB) : static_cast<E*>(rA));
+
+                T hz[kQ];
+                // prologue: planes zs-1 (densities only) and zs (to hs)
+                issue(wrapz(zs - 1), qme, r_odd);
+                if constexpr (DEEP) issue(zs, qme, r_even);
+                stage_pipe(wrapz(zs - 1), rslot(zs - 1), -1, ahead(zs - 1), hz, r_odd);
+                stage_pipe(zs, rslot(zs), jslot(zs), ahead(zs), hz, r_even);
+                // unrolled by two so the register sets keep fixed names; every
+                // wave, in either role, passes ze - zs barriers
+                for (int z = zs; z < ze; z += 2) {
+                    stage_pipe(wrapz(z + 1), rslot(z + 1), jslot(z + 1), ahead(z + 1), hz, r_odd);
+                    __syncthreads();
+                    collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hz, false);
+                    if (z + 1 >= ze) break;
+                    stage_pipe(wrapz(z + 2), rslot(z + 2), jslot(z + 2), ahead(z + 2), hz, r_even);
+                    __syncthreads();
+                    collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), jslot(z + 1), hz, false);
+                }
+            };
+            const bool wave_ring = NC == 2 && __builtin_amdgcn_ballot_w64(ring) != 0;
+            if (wave_ring) sweep(std::true_type{});
+            else sweep(std::false_type{});
         }
     } else {
         T hA[kQ];
