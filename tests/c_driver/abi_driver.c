@@ -7,7 +7,10 @@
  *   2. 200 steps conserve each component's mass (Eq. rho_BGK sums) to 1e-12;
  *   3. a checkpoint taken with lbm_get_populations and restored with
  *      lbm_set_populations / lbm_set_time continues bit for bit like the
- *      uninterrupted run (FP64 totals and densities after 50 more steps).
+ *      uninterrupted run (FP64 totals and densities after 50 more steps);
+ *   4. a server (shortest-first sharing, two slots) serves three requests of
+ *      the same problem with different step budgets; each result's densities
+ *      and totals equal those of a context stepped alone as far.
  * Prints "C ABI OK" and exits 0 on success, 1 otherwise. */
 #include <math.h>
 #include <stdio.h>
@@ -90,9 +93,53 @@ int main(void)
         memcmp(ta.momentum, tb.momentum, sizeof(ta.momentum)) != 0 || ta.time != 250 || tb.time != 250)
         return fail("checkpoint restart differs", 0);
     free(f);
+    lbm_destroy(ctx);
+
+    lbm_server_cfg cfg;
+    memset(&cfg, 0, sizeof(cfg));
+    cfg.max_slots = 2;
+    cfg.steps_per_tick = 16;
+    cfg.storage = LBM_F64;
+    cfg.ncomp = 2;
+    cfg.c_ns = 1;
+    cfg.max_cells = N;
+    cfg.policy = LBM_SERVE_SHORTEST_FIRST;
+    lbm_server* srv = NULL;
+    if ((rc = lbm_server_create(&cfg, NULL, &srv)) != LBM_OK) return fail("lbm_server_create", rc);
+    const int64_t budget[3] = {70, 16, 33};
+    uint64_t ticket[3];
+    double* out[3];
+    for (int k = 0; k < 3; ++k) {
+        out[k] = malloc(sizeof(double) * 2 * N);
+        if (!out[k]) return fail("malloc", 0);
+        lbm_request rq;
+        memset(&rq, 0, sizeof(rq));
+        rq.dom = d;
+        rq.n_s = ns;
+        rq.rho_init = rho;
+        rq.params = p;
+        rq.max_steps = budget[k];
+        rq.rho_out = out[k];
+        if ((rc = lbm_batch_submit(srv, &rq, &ticket[k])) != LBM_OK) return fail("lbm_batch_submit", rc);
+    }
+    for (int k = 0; k < 3; ++k) {
+        lbm_result res;
+        if ((rc = lbm_batch_wait(srv, ticket[k], 60.0, &res)) != LBM_OK) return fail("lbm_batch_wait", rc);
+        if (res.status != LBM_OK || res.steps_done != budget[k]) return fail("request status", res.status);
+        lbm_ctx* alone = NULL;
+        if ((rc = lbm_create(&d, ns, rho, &p, NULL, NULL, &alone)) != LBM_OK) return fail("lbm_create", rc);
+        if ((rc = lbm_step(alone, budget[k])) != LBM_OK) return fail("lbm_step", rc);
+        if ((rc = lbm_moments(alone, ra, NULL, NULL, &ta)) != LBM_OK) return fail("lbm_moments", rc);
+        lbm_destroy(alone);
+        if (memcmp(ra, out[k], sizeof(double) * 2 * N) != 0 ||
+            memcmp(ta.mass, res.totals.mass, sizeof(ta.mass)) != 0 ||
+            memcmp(ta.momentum, res.totals.momentum, sizeof(ta.momentum)) != 0)
+            return fail("served result differs from the context stepped alone", k);
+        free(out[k]);
+    }
+    lbm_server_destroy(srv);
     free(ra);
     free(rb);
-    lbm_destroy(ctx);
     printf("mass %.17g %.17g  momentum %.3e %.3e %.3e\nC ABI OK\n", t1.mass[0], t1.mass[1], t1.momentum[0],
            t1.momentum[1], t1.momentum[2]);
     return 0;

@@ -1,7 +1,8 @@
 """The C ABI driven from a plain C program on the GPU (no Python or PyTorch in
 the process): parameter rejection, FP64 mass conservation over 200 steps of a
-ragged two-component gray domain with solid voxels and adhesion, and a
-bit-for-bit checkpoint restart (tests/c_driver/abi_driver.c)."""
+ragged two-component gray domain with solid voxels and adhesion, a
+bit-for-bit checkpoint restart, and a shortest-first server whose results
+equal contexts stepped alone (tests/c_driver/abi_driver.c)."""
 import subprocess
 
 import pytest
