@@ -856,6 +856,47 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                                     static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};
             pull_raw<ST>(ra, dir_bytes, so, q, e);
         };
+        if (sizeof(E) != 2 && a.nz == 1) {
+            // One cell deep: planes z - 1, z and z + 1 are all plane 0, so it
+            // is staged once and collided against itself (one memory round
+            // trip per step instead of the sweep's three; the three slots the
+            // sweep would fill hold the same values).  Not for the 16-bit
+            // formats: the extra path cost their 3-D sweep registers and 16 %.
+            const int slot = rslot(0), js = jslot(0);
+            E r1[kQ];
+            E r2[NC == 2 ? kQ : 1];
+            issue(0, qme, r1);
+            if constexpr (NC == 2) issue(0, qr, r2);
+            float nsv[NSMAX][CNS];
+#pragma unroll
+            for (int k = 0; k < NSMAX; ++k)
+#pragma unroll
+                for (int c = 0; c < CNS; ++c) nsv[k][c] = ns[static_cast<size_t>(c) * a.N + no[k]];
+            T h[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) h[i] = ST::dec(r1[i], a.inv_scale);
+            reservoir_override(x, y, 0, h);
+            s_rho[slot][s][me] = a.rho0[s] + sum19(h);
+            if constexpr (NC == 2) {
+                s_j[js][s][0][tj] = first_moment<T, 0>(h);
+                s_j[js][s][1][tj] = first_moment<T, 1>(h);
+                s_j[js][s][2][tj] = first_moment<T, 2>(h);
+                if (ring) {
+                    T hr[kQ];
+#pragma unroll
+                    for (int i = 0; i < kQ; ++i) hr[i] = ST::dec(r2[i], a.inv_scale);
+                    reservoir_override(rx, ry, 0, hr);
+                    s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NSMAX; ++k)
+#pragma unroll
+                for (int c = 0; c < CNS; ++c) s_ns[slot][c][nl[k]] = nsv[k][c];
+            __syncthreads();
+            collide(0, slot, slot, slot, js, h, false);
+            return;
+        }
         if constexpr (sizeof(E) != 2) {
             E rr[kQ];  // own populations of the next plane to stage, raw
             E er[kQ];  // ring populations of the plane being staged, raw
