@@ -611,7 +611,7 @@ struct TileShared {
 
 // The sweep of one tile column (logical tile index L of the domain described
 // by a).  Shared by the single-domain and the batched kernels.
-template <typename ST, int NC, int CNS, int TX, int TY, int FS>
+template <typename ST, int NC, int CNS, int TX, int TY, int FS, bool ONE = false>
 __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const typename ST::E* __restrict__ A,
                                           typename ST::E* __restrict__ B, const float* __restrict__ ns, int L,
                                           uint32_t t, TileShared<ST, NC, CNS, TX, TY>& sh)
@@ -856,12 +856,13 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                                     static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};
             pull_raw<ST>(ra, dir_bytes, so, q, e);
         };
-        if (sizeof(E) != 2 && a.nz == 1) {
-            // One cell deep: planes z - 1, z and z + 1 are all plane 0, so it
-            // is staged once and collided against itself (one memory round
-            // trip per step instead of the sweep's three; the three slots the
-            // sweep would fill hold the same values).  Not for the 16-bit
-            // formats: the extra path cost their 3-D sweep registers and 16 %.
+        if constexpr (ONE) {
+            // One cell deep (the instance launched for nz = 1): planes z - 1,
+            // z and z + 1 are all plane 0, so it is staged once and collided
+            // against itself (one memory round trip per step instead of the
+            // sweep's three; the three slots the sweep would fill hold the
+            // same values).  A kernel of its own: as a branch in the 3-D
+            // kernels it changed their register allocation.
             const int slot = rslot(0), js = jslot(0);
             E r1[kQ];
             E r2[NC == 2 ? kQ : 1];
@@ -1077,7 +1078,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     }
 }
 
-template <typename ST, int NC, int CNS, int TX, int TY, int FS>
+template <typename ST, int NC, int CNS, int TX, int TY, int FS, bool ONE>
 __global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
                                                       const typename ST::E* __restrict__ A,
                                                       typename ST::E* __restrict__ B,
@@ -1089,7 +1090,7 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
     const int nb = gridDim.x;
     int L = blockIdx.x;
     if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    step_tile<ST, NC, CNS, TX, TY, FS>(a, A, B, ns, L, a.t, sh);
+    step_tile<ST, NC, CNS, TX, TY, FS, ONE>(a, A, B, ns, L, a.t, sh);
 }
 
 
@@ -1403,7 +1404,7 @@ int storage_bytes(int storage)
     }
 }
 
-template <typename ST, int NC, int CNS, int TX, int TY, int FS>
+template <typename ST, int NC, int CNS, int TX, int TY, int FS, bool ONE>
 static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
                          hipStream_t st)
 {
@@ -1416,7 +1417,7 @@ static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const voi
     a.nzc = (p.nz + l.zchunk - 1) / l.zchunk;
     a.t = static_cast<uint32_t>(t);
     const int nblocks = a.ntx * a.nty * a.nzc;
-    hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS>), dim3(nblocks), dim3(NC * TX * TY), 0, st, a,
+    hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE>), dim3(nblocks), dim3(NC * TX * TY), 0, st, a,
                        static_cast<const E*>(A), static_cast<E*>(B), ns);
     return hipGetLastError();
 }
@@ -1427,17 +1428,27 @@ static hipError_t step_ty(const Problem& p, const Launch& l, int64_t t, const vo
                           hipStream_t st)
 {
     constexpr int SC = kForcingShanChen, GUO = kForcingGuo;
+    // one-cell-deep domains on the default tiles: the one-plane instances
+    const bool one = p.nz == 1;
     if (p.forcing == kForcingGuo) {  // the GS-WBS: the default tiles only
-        if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8, GUO>(p, l, t, A, B, ns, st);
-        if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4, GUO>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 64 && l.tile_y == 8)
+            return one ? step_t<ST, NC, CNS, 64, 8, GUO, true>(p, l, t, A, B, ns, st)
+                       : step_t<ST, NC, CNS, 64, 8, GUO, false>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 64 && l.tile_y == 4)
+            return one ? step_t<ST, NC, CNS, 64, 4, GUO, true>(p, l, t, A, B, ns, st)
+                       : step_t<ST, NC, CNS, 64, 4, GUO, false>(p, l, t, A, B, ns, st);
         return hipErrorInvalidValue;
     }
-    if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4, SC>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 64 && l.tile_y == 4) return step_t<ST, NC, CNS, 64, 4, SC>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 64 && l.tile_y == 8) return step_t<ST, NC, CNS, 64, 8, SC>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4, SC>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8, SC>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16, SC>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 64 && l.tile_y == 8)
+        return one ? step_t<ST, NC, CNS, 64, 8, SC, true>(p, l, t, A, B, ns, st)
+                   : step_t<ST, NC, CNS, 64, 8, SC, false>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 64 && l.tile_y == 4)
+        return one ? step_t<ST, NC, CNS, 64, 4, SC, true>(p, l, t, A, B, ns, st)
+                   : step_t<ST, NC, CNS, 64, 4, SC, false>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4, SC, false>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4, SC, false>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8, SC, false>(p, l, t, A, B, ns, st);
+    if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16, SC, false>(p, l, t, A, B, ns, st);
     return hipErrorInvalidValue;
 }
 
