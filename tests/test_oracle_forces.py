@@ -72,3 +72,32 @@ def test_wetting_sign_convention():
     m = o.moments(o.init(rho))
     fx = m["ftot"][:, 0, 0, :, 2:-2]
     assert (fx[0] > 0).all() and (fx[1] < 0).all()
+
+
+@pytest.mark.parametrize("lattice", [19, 9])
+def test_adhesion_reads_each_components_own_field(lattice):
+    """With two n_s fields (c_ns = 2) the adhesion force of component s
+    follows the gradient of its own field: n_s,1 ramps along x, n_s,2 along y,
+    so F_ads,1 has no y part and F_ads,2 no x part."""
+    nx, ny = 16, 7
+    nz = 5 if lattice == 19 else 1
+    x = np.arange(nx)[None, None, :]
+    y = np.arange(ny)[None, :, None]
+    rho = np.empty((2, nz, ny, nx))
+    rho[0] = 0.3 + 0.02 * x + 0 * y
+    rho[1] = 0.45 + 0 * x + 0.01 * y
+    ns = np.empty((2, nz, ny, nx), np.float32)
+    ns[0] = np.broadcast_to(0.125 + 0.03125 * x + 0 * y, (nz, ny, nx))
+    ns[1] = np.broadcast_to(0.0625 + 0 * x + 0.0625 * y, (nz, ny, nx))
+    G, G_ads = 1.3, (-0.2, 0.35)
+    o = Oracle(Setup((nx, ny, nz), ncomp=2, c_ns=2, G=G, G_ads=G_ads, lattice=lattice), ns.astype(np.float64))
+    m = o.moments(o.init(rho))
+    grad_rho = [np.array([0.02, 0.0, 0.0]), np.array([0.0, 0.01, 0.0])]
+    grad_ns = [np.array([0.03125, 0.0, 0.0]), np.array([0.0, 0.0625, 0.0])]
+    sl = (slice(None), slice(1, ny - 1), slice(1, nx - 1))
+    cs2 = 1.0 / 3.0
+    for s in range(2):
+        r_s = rho[s][sl]
+        for a in range(3):
+            want = -G * r_s * cs2 * grad_rho[1 - s][a] - G_ads[s] * r_s * cs2 * grad_ns[s][a]
+            assert np.abs(m["ftot"][s, a][sl] - want).max() < 1e-15, (s, a)

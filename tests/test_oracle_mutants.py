@@ -40,6 +40,8 @@ MUTANTS = [
     ("force shift without tau", "p->tau[s] * Ft[s][a] / rho_s[s]", "Ft[s][a] / rho_s[s]", 1),
     ("common velocity not tau-weighted", "num[a] += j[s][a] / p->tau[s];", "num[a] += j[s][a];", 1),
     ("macroscopic velocity without the half force", "(js + Ft[s][a] / 2.0)", "(js + Ft[s][a])", 1),
+    ("adhesion reads component 0's n_s field", "const double s_nb = ns_at(p, ns, s, nb);",
+     "const double s_nb = ns_at(p, ns, 0, nb);", 1),
     ("one n_s field for both components", "return ns[(p->c_ns == 2 ? s : 0) * ncells(p) + n];",
      "return ns[n];", 1),
     ("macroscopic velocity not weighted by 1 - n_s", "m += (1.0 - ns_at(p, ns, s, n)) * (js", "m += (js", 1),
