@@ -138,3 +138,21 @@ def test_per_component_bounce_back_fractions():
         for s in range(2):
             for a in range(3):
                 assert np.allclose(got[s, a], j[s, a], rtol=1e-11, atol=1e-16), (t, s, a)
+
+
+@pytest.mark.parametrize("n", [0.1, 0.5])
+def test_two_component_permeability_law(n):
+    """Two components with equal tau in a uniform medium: the mixture obeys
+    the same law, rho u_macro = (1 - n) F / (2n) with rho the total density
+    (Eq. HMCSC_u_macro sums both components and divides by rho)."""
+    tau = 0.8
+    nu = CS2 * (tau - 0.5)
+    F = 1e-5
+    st = Setup((2, 2, 2), ncomp=2, tau=(tau, tau), G=0.9, F_ext=(F, 0, 0))
+    w = inputs.uniform((2, 2, 2), ns_value=n, rho=(0.7, 0.4))
+    o = Oracle(st, w.ns)
+    nn = np.float64(np.float32(n))
+    steps = int(np.ceil(np.log(1e-14) / np.log(abs(1 - 2 * nn)))) + 2 if nn != 0.5 else 2
+    m = o.moments(o.run(o.init(w.rho), steps))
+    rho_u = (m["rho"].sum(0) * m["u"][0]).mean()
+    assert abs(nu * rho_u / F - (1 - nn) * nu / (2 * nn)) < 1e-10 * (1 - nn) * nu / (2 * nn)

@@ -18,7 +18,8 @@ from oracle import ref
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TESTS = os.path.join(ROOT, "tests")
 PINS = ["test_oracle_forces.py", "test_oracle_closed_forms.py", "test_oracle_invariants.py",
-        "test_oracle_lattice.py", "test_oracle_shear_wave.py", "test_oracle_brinkman.py", "test_oracle_guo.py"]
+        "test_oracle_lattice.py", "test_oracle_shear_wave.py", "test_oracle_brinkman.py", "test_oracle_guo.py",
+        "test_oracle_pressure.py"]
 
 # (name, text in hmcsc_oracle.c, replacement, which occurrence (1-based))
 MUTANTS = [
@@ -42,6 +43,11 @@ MUTANTS = [
     ("macroscopic velocity without the half force", "(js + Ft[s][a] / 2.0)", "(js + Ft[s][a])", 1),
     ("adhesion reads component 0's n_s field", "const double s_nb = ns_at(p, ns, s, nb);",
      "const double s_nb = ns_at(p, ns, 0, nb);", 1),
+    ("pressure without the interaction term", "pr[n] = CS2 * (rho_tot + inter);", "pr[n] = CS2 * rho_tot;", 1),
+    ("pressure interaction without the stencil scale", "p->g_scale * p->G * rf[n] * rf[N + n]",
+     "p->G * rf[n] * rf[N + n]", 1),
+    ("u_macro divided by the first component's density", "u[a * N + n] = rho_tot > 0.0 ? m / rho_tot : 0.0;",
+     "u[a * N + n] = rf[n] > 0.0 ? m / rf[n] : 0.0;", 1),
     ("one n_s field for both components", "return ns[(p->c_ns == 2 ? s : 0) * ncells(p) + n];",
      "return ns[n];", 1),
     ("macroscopic velocity not weighted by 1 - n_s", "m += (1.0 - ns_at(p, ns, s, n)) * (js", "m += (js", 1),
