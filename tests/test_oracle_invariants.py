@@ -141,6 +141,26 @@ def test_reservoir_cells_hold_rest_equilibrium():
     assert np.allclose(f[1, :, :2], W19[:, None, None, None] * 0.03, rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_reservoir_slab_is_exactly_lo_to_hi(axis):
+    """A reservoir covers exactly the cells with lo <= coordinate[axis] < hi:
+    after a step those hold w_i rho_res, their neighbours just outside the
+    slab (coordinate lo - 1 and hi) do not."""
+    shape = (7, 8, 9)
+    w = inputs.random_state(shape, 13, ns_choices=[0.0, 0.5])
+    lo, hi = 2, 5
+    st = Setup(shape, ncomp=2, tau=(1.0, 1.0), G=0.9, F_ext=(1e-4, -1e-4, 1e-4),
+               reservoirs=[Reservoir(axis, lo, hi, (0.8, 0.2))])
+    o = Oracle(st, w.ns)
+    f = o.run(o.init(w.rho), 3)
+    # populations are [s, i, z, y, x]: move the reservoir axis to the front
+    g = np.moveaxis(f, {0: 4, 1: 3, 2: 2}[axis], 2)
+    for s, r in ((0, 0.8), (1, 0.2)):
+        assert np.array_equal(g[s, :, lo:hi], np.broadcast_to(W19[:, None, None, None] * r, g[s, :, lo:hi].shape))
+        for c in (lo - 1, hi):
+            assert not np.allclose(g[s, :, c], W19[:, None, None] * r, rtol=0, atol=1e-12)
+
+
 def test_cell_update_matches_full_step():
     shape = (6, 7, 5)
     w = inputs.random_state(shape, 31, c_ns=2, ns_choices=[0.0, 0.3, 1.0])

@@ -48,6 +48,9 @@ MUTANTS = [
      "p->G * rf[n] * rf[N + n]", 1),
     ("u_macro divided by the first component's density", "u[a * N + n] = rho_tot > 0.0 ? m / rho_tot : 0.0;",
      "u[a * N + n] = rf[n] > 0.0 ? m / rf[n] : 0.0;", 1),
+    ("reservoir range closed at hi", "xyz[p->res[r].axis] < p->res[r].hi", "xyz[p->res[r].axis] <= p->res[r].hi", 1),
+    ("reservoir axis ignored", "xyz[p->res[r].axis] >= p->res[r].lo && xyz[p->res[r].axis] < p->res[r].hi",
+     "xyz[2] >= p->res[r].lo && xyz[2] < p->res[r].hi", 1),
     ("one n_s field for both components", "return ns[(p->c_ns == 2 ? s : 0) * ncells(p) + n];",
      "return ns[n];", 1),
     ("macroscopic velocity not weighted by 1 - n_s", "m += (1.0 - ns_at(p, ns, s, n)) * (js", "m += (js", 1),
