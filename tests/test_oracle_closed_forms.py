@@ -138,6 +138,11 @@ def test_per_component_bounce_back_fractions():
         for s in range(2):
             for a in range(3):
                 assert np.allclose(got[s, a], j[s, a], rtol=1e-11, atol=1e-16), (t, s, a)
+    # Eq. (HMCSC_u_macro) with each component's own fraction, from the same j
+    u = sum((1 - nn[s]) * (j[s] + rho_s[s] / rho * F / 2) for s in range(2)) / rho
+    got_u = o.moments(f)["u"]
+    for a in range(3):
+        assert np.allclose(got_u[a], u[a], rtol=1e-11, atol=1e-16), a
 
 
 @pytest.mark.parametrize("n", [0.1, 0.5])

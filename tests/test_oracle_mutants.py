@@ -51,6 +51,8 @@ MUTANTS = [
     ("reservoir range closed at hi", "xyz[p->res[r].axis] < p->res[r].hi", "xyz[p->res[r].axis] <= p->res[r].hi", 1),
     ("reservoir axis ignored", "xyz[p->res[r].axis] >= p->res[r].lo && xyz[p->res[r].axis] < p->res[r].hi",
      "xyz[2] >= p->res[r].lo && xyz[2] < p->res[r].hi", 1),
+    ("u_macro reads component 0's n_s field", "m += (1.0 - ns_at(p, ns, s, n)) * (js + Ft[s][a] / 2.0);",
+     "m += (1.0 - ns_at(p, ns, 0, n)) * (js + Ft[s][a] / 2.0);", 1),
     ("one n_s field for both components", "return ns[(p->c_ns == 2 ? s : 0) * ncells(p) + n];",
      "return ns[n];", 1),
     ("macroscopic velocity not weighted by 1 - n_s", "m += (1.0 - ns_at(p, ns, s, n)) * (js", "m += (js", 1),
