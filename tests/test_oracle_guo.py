@@ -76,6 +76,31 @@ def test_gswbs_uniform_medium_momentum_map(ns, tau):
     assert abs(f[0].sum() / 8 - rho) < 1e-14
 
 
+@pytest.mark.parametrize("ns", [0.0, 0.3])
+def test_gswbs_two_component_momentum_map(ns):
+    """The same map per component, two components with unequal tau and
+    density: each relaxes towards rho_s u with its own tau_s and receives its
+    own share F_s = rho_s / rho F of the force through its own prefactor
+    1 - 1/(2 tau_s); u = sum_s (1 - n)(j_s + F_s/2) / rho is common."""
+    c, w, _ = _lat()
+    F = np.array([2e-5, -1e-5, 3e-5])
+    tau = (0.7, 1.4)
+    rho_s = np.array([0.9, 0.3])
+    rho = rho_s.sum()
+    o = _oracle((2, 2, 2), np.full((1, 2, 2, 2), ns), ncomp=2, tau=tau, G=0.9, F_ext=tuple(F))
+    f = o.init(np.stack([np.full((1, 2, 2, 2), r) for r in rho_s]).reshape(2, 2, 2, 2))
+    j = np.zeros((2, 3))
+    Fs = [rho_s[s] / rho * F for s in range(2)]
+    for _ in range(40):
+        f = o.step(f)
+        u = sum((1 - ns) * (j[s] + Fs[s] / 2) for s in range(2)) / rho
+        j = np.array([(1 - ns) * j[s] - (1 - ns) / tau[s] * (j[s] - rho_s[s] * u) - ns * j[s]
+                      + (1 - ns) * (1 - 1 / (2 * tau[s])) * Fs[s] for s in range(2)])
+        for s in range(2):
+            jg = np.einsum("izyx,ia->a", f[s], c) / 8
+            np.testing.assert_allclose(jg, j[s], rtol=1e-11, atol=1e-16)
+
+
 def test_gswbs_full_bounce_back_has_period_two():
     rng = np.random.default_rng(3)
     shape = (5, 4, 3)

@@ -53,6 +53,10 @@ MUTANTS = [
      "xyz[2] >= p->res[r].lo && xyz[2] < p->res[r].hi", 1),
     ("u_macro reads component 0's n_s field", "m += (1.0 - ns_at(p, ns, s, n)) * (js + Ft[s][a] / 2.0);",
      "m += (1.0 - ns_at(p, ns, 0, n)) * (js + Ft[s][a] / 2.0);", 1),
+    ("Guo term with the first component's tau", "guo_term(L, i, p->tau[s], ueq, Ft[s])",
+     "guo_term(L, i, p->tau[0], ueq, Ft[s])", 1),
+    ("Guo term with the other component's force", "guo_term(L, i, p->tau[s], ueq, Ft[s])",
+     "guo_term(L, i, p->tau[s], ueq, Ft[1 - s < p->ncomp ? 1 - s : 0])", 1),
     ("one n_s field for both components", "return ns[(p->c_ns == 2 ? s : 0) * ncells(p) + n];",
      "return ns[n];", 1),
     ("macroscopic velocity not weighted by 1 - n_s", "m += (1.0 - ns_at(p, ns, s, n)) * (js", "m += (js", 1),
