@@ -162,7 +162,7 @@ def ensemble(storage="f16s", ndom=64, steps=100, warmup=10, seed=3000):
             "edges": {int(e): int((edges == e).sum()) for e in sorted(set(edges.tolist()))}}
 
 
-def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0, tile_x=64,
+def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0, tile_x=0,
             policy="fair", run_cells=0):
     """Continuous-batching serving: Poisson arrivals at `rate` per second for
     `seconds`, each a porous domain of edge U{48..192} asking for U{2000..20000}
@@ -183,7 +183,7 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
         if (k + 1) % 20 == 0:
             print(f"# serving: generated {k + 1}/{len(arrivals)} requests", file=sys.stderr, flush=True)
     srv = lbm.Server(storage=storage, max_slots=64, steps_per_tick=steps_per_tick, max_cells=192 ** 3,
-                     tile=(tile_x, 8), policy=policy,
+                     tile=(tile_x, 8 if tile_x else 0), policy=policy,
                      run_cells=run_cells)
     t0 = time.perf_counter()
     tickets = []
@@ -311,8 +311,8 @@ def main():
                     help="how the server shares each tick among resident requests")
     ap.add_argument("--serve-run-cells", type=int, default=0,
                     help="shortest-first: cells stepped per tick at least (0: the library default)")
-    ap.add_argument("--serve-tile", type=int, default=64, choices=(32, 64),
-                    help="tile width of the batched kernel in the server")
+    ap.add_argument("--serve-tile", type=int, default=0, choices=(0, 32, 64),
+                    help="tile width of the batched kernel in the server (0: the library default)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (counter calibration)")
     args = ap.parse_args()

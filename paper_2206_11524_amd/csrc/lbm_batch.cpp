@@ -45,7 +45,7 @@ class BatchRunner {
         kmax_ = std::max(1, k_graph);
         stream_ = st;
         bytes_ = hm::batch_table_bytes(storage, max_domains);
-        if (!hm::batch_tile_supported(tx_, ty_)) return LBM_EINVAL;
+        if (!hm::batch_tile_supported(storage, ncomp, tx_, ty_)) return LBM_EINVAL;
         int dev = 0, cus = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -231,16 +231,23 @@ int lbm_group_create(lbm_ctx* const* ctxs, int32_t n, lbm_group** out)
     if (!ctxs || n < 1) return LBM_EINVAL;
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return LBM_EINVAL;
+        // one format per batched kernel, which runs the HMCSC only; one stream,
+        // so the group's launches and each context's own calls stay ordered;
+        // no health check (the group has no per-step totals)
         if (ctxs[i]->prm.storage != ctxs[0]->prm.storage || ctxs[i]->prm.ncomp != ctxs[0]->prm.ncomp ||
             ctxs[i]->prm.c_ns != ctxs[0]->prm.c_ns || ctxs[i]->device != ctxs[0]->device ||
-            ctxs[i]->prm.forcing != LBM_FORCING_SHAN_CHEN)  // the batched kernel runs the HMCSC only
+            ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->prm.forcing != LBM_FORCING_SHAN_CHEN ||
+            ctxs[i]->prm.check_every != 0)
             return LBM_EINVAL;
     }
     lbm_group* g = new (std::nothrow) lbm_group();
     if (!g) return LBM_ENOMEM;
     g->ctx.assign(ctxs, ctxs + n);
     const lbm_params& p = ctxs[0]->prm;
-    const int tx = hm_rt::env_int("LBM_BATCH_TILE_X", 64), ty = 8;
+    int tx = 64, ty = 8;
+    hm::batch_default_tile(p.storage, p.ncomp, &tx, &ty);
+    tx = hm_rt::env_int("LBM_BATCH_TILE_X", tx);
+    ty = hm_rt::env_int("LBM_BATCH_TILE_Y", ty);
     const int rc = g->runner.init(p.storage, p.ncomp, p.c_ns, tx, ty, n, hm_rt::env_int("LBM_GRAPH_STEPS", 16),
                                   ctxs[0]->stream);
     if (rc) {
@@ -540,12 +547,14 @@ int lbm_server_create(const lbm_server_cfg* cfg, void* reserved, lbm_server** ou
     if (cfg->max_slots < 1 || cfg->steps_per_tick < 1 || cfg->max_cells < 1) return LBM_EINVAL;
     if (cfg->storage < LBM_F64 || cfg->storage > LBM_BF16S) return LBM_EINVAL;
     if (cfg->ncomp < 1 || cfg->ncomp > 2 || cfg->c_ns < 1 || cfg->c_ns > cfg->ncomp) return LBM_EINVAL;
-    if (cfg->max_cells >= (int64_t(1) << 31)) return LBM_EINVAL;
     if (cfg->policy < LBM_SERVE_FAIR || cfg->policy > LBM_SERVE_SHORTEST_FIRST || cfg->pad != 0 ||
         cfg->run_cells < 0)
         return LBM_EINVAL;
-    const int tx = cfg->tile_x ? cfg->tile_x : 64, ty = cfg->tile_y ? cfg->tile_y : 8;
-    if (!hm::batch_tile_supported(tx, ty)) return LBM_EINVAL;
+    int tx = 64, ty = 8;
+    hm::batch_default_tile(cfg->storage, cfg->ncomp, &tx, &ty);
+    if (cfg->tile_x) tx = cfg->tile_x;
+    if (cfg->tile_y) ty = cfg->tile_y;
+    if (!hm::batch_tile_supported(cfg->storage, cfg->ncomp, tx, ty)) return LBM_EINVAL;
     lbm_server* s = new (std::nothrow) lbm_server();
     if (!s) return LBM_ENOMEM;
     s->cfg = *cfg;

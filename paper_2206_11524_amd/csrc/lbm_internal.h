@@ -27,7 +27,7 @@ inline ScratchLayout scratch_layout(int64_t N, int ncomp)
     s.rho = off; off = align_up(off + sizeof(double) * static_cast<size_t>(ncomp) * N);
     s.u = off; off = align_up(off + sizeof(double) * 3 * static_cast<size_t>(N));
     s.p = off; off = align_up(off + sizeof(double) * static_cast<size_t>(N));
-    s.partials = off; off = align_up(off + sizeof(double) * 6 * hm::moments_max_blocks());
+    s.partials = off; off = align_up(off + sizeof(double) * 10 * hm::moments_max_blocks());
     s.totals = off; off = align_up(off + sizeof(double) * 6);
     s.bytes = off;
     return s;
@@ -60,6 +60,8 @@ struct lbm_ctx {
 };
 
 namespace hm_rt {
-// FP64 totals (and, if fields, per-cell moments into scratch) of the current state.
-int compute_totals(lbm_ctx* c, bool fields, lbm_totals* tot);
+// FP64 totals (and, if fields, per-cell moments into scratch) of the current
+// state.  With forces false only the mass and the local part of the momentum
+// are summed (the health check).
+int compute_totals(lbm_ctx* c, bool fields, bool forces, lbm_totals* tot);
 }  // namespace hm_rt

@@ -37,12 +37,18 @@ struct Problem {
 
 struct Launch {
     int tile_x;   // cells per tile row (32, 64 or 128)
-    int tile_y;   // rows per tile (4 with 128-wide rows; 4 or 8 with 64; 4, 8 or 16 with 32)
+    int tile_y;   // rows per tile (split layout: 4 with 128-wide rows, 4 or 8 with 64, 4, 8
+                  // or 16 with 32; pair layout: 4, 8 or 16 with 64)
     int zchunk;   // planes per block
 };
 
-// True if the tile shape is compiled in.
-bool tile_supported(int tile_x, int tile_y);
+// True if two components in this format use the pair layout: both values of
+// one (cell, direction) in one 32-bit word, plane blocks [z][i][y][x][s]; all
+// other runs use the split layout [s][z][i][y][x].
+bool pair_layout(int storage, int ncomp);
+
+// True if the tile shape is compiled in for this format and component count.
+bool tile_supported(int storage, int ncomp, int tile_x, int tile_y);
 
 // Bytes per stored population.
 int storage_bytes(int storage);
@@ -64,18 +70,14 @@ hipError_t launch_canonical(const Problem& p, const void* A, int s, int i, doubl
 hipError_t launch_set_canonical(const Problem& p, const double* in, int s, int i, void* A,
                                 hipStream_t st);
 
-// FP64 densities rho[s*N + n] of the current state.
-hipError_t launch_density(const Problem& p, const void* A, double* rho, hipStream_t st);
-
-// FP64 moments from the state and its densities; per-block partial totals
-// (mass[2], momentum[3]) to partials[nblocks*5]; fields optional (NULL).
-// Returns the number of blocks used in *nblocks.
-hipError_t launch_moments(const Problem& p, const void* A, const float* ns, const double* rho,
-                          double* u, double* pr, double* partials, int* nblocks,
-                          hipStream_t st);
-
-// Deterministic sum of nblocks partials (5 doubles each) into out[5].
-hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
+// FP64 diagnostics of the state in A: densities rho [ncomp][N] (always),
+// u_macro [3][N] and p [N] when not NULL, and the totals out[5] = {M_0, M_1,
+// J_x, J_y, J_z} with J = sum rho u_macro, deterministic (fixed-order
+// reductions).  With forces false only the first pass runs: rho and the
+// local part of J, sum (1 - n_s)(j + F_ext/2), enough for a health check;
+// u and p need forces.  partials holds 10 * moments_max_blocks() doubles.
+hipError_t launch_diagnostics(const Problem& p, const void* A, const float* ns, bool forces, double* rho,
+                              double* u, double* pr, double* partials, double* out, hipStream_t st);
 
 int moments_max_blocks();
 
@@ -112,8 +114,9 @@ size_t batch_table_bytes(int storage, int max_domains);
 // returns the total number of tiles.  Upload it to the device before launching.
 int batch_encode(int storage, const BatchDomain* d, int n, int tile_x, int tile_y, void* host);
 
-// Tile shapes compiled for the batched kernel.
-bool batch_tile_supported(int tile_x, int tile_y);
+// Tile shapes compiled for the batched kernel, and the default one.
+bool batch_tile_supported(int storage, int ncomp, int tile_x, int tile_y);
+void batch_default_tile(int storage, int ncomp, int* tile_x, int* tile_y);
 
 // Blocks of the batched kernel that fit one CU at once (registers, LDS); at
 // least 1.

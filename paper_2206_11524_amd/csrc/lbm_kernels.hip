@@ -1,26 +1,35 @@
 // HIP kernels (gfx950) of the HMCSC lattice Boltzmann update.
 //
-// Layout in HBM: populations are structure-of-arrays, P[(s*19 + i)*N + n] with
-// n = (z*ny + y)*nx + x.  Streaming is "pull": a buffer holds the populations
-// that left each cell at the previous step, so the pre-collision state of
-// Eq. (LGS) at cell x is f_i(x) = P_i(x - c_i) (periodic).  Every stored value is
-// shifted, h = f - w_i*rho0_s (scaled by 2^k for the 16-bit formats); the whole
+// Layout in HBM: populations are grouped by plane.  For one component the 19
+// direction arrays of plane z lie next to each other, P[((s*nz + z)*19 + i)*
+// plane + n], n = y*nx + x the in-plane index ("split" layout, FP64, FP32 and
+// single-component runs).  Two-component runs in the 16-bit formats keep the
+// two components of one (cell, direction) in one 32-bit word, P[(((z*19 + i)*
+// plane + n) << 1) + s] ("pair" layout), so one 4-byte load brings both.
+// Streaming is "pull": a buffer holds the populations that left each cell at
+// the previous step, so the pre-collision state of Eq. (LGS) at cell x is
+// f_i(x) = P_i(x - c_i) (periodic).  Every stored value is shifted,
+// h = f - w_i*rho0_s (scaled by 2^k for the 16-bit formats); the whole
 // collision is written in the shifted variables (the shift cancels in the
 // partial bounce-back blend because w_ibar = w_i), which keeps small deviations
 // representable in reduced precision.
 //
-// The step kernel is a fused 2.5-D sweep: a block owns a 64 x TY column of
+// The step kernels are fused 2.5-D sweeps: a block owns a TX x TY column of
 // cells and marches along z.  For every plane it pulls the populations of its
-// cells once (kept in registers for the collision of the next iteration),
-// forms the densities, and stages them in LDS together with a one-cell ring of
-// densities recomputed from the ring cells' populations, plus the n_s field.
-// The cohesion force (Eq. SC_F_inter) and adhesion force (Eq. SC_F_ads) then
-// read their 18 neighbours from LDS, so HBM sees each population read once
-// and written once per step (ring and z-halo re-reads hit L2/MALL).
+// cells once (kept for the collision of a later iteration), forms the
+// densities, and stages them in LDS together with a one-cell ring of densities
+// recomputed from the ring cells' populations, plus the n_s field.  The
+// cohesion force (Eq. SC_F_inter) and adhesion force (Eq. SC_F_ads) then read
+// their 18 neighbours from LDS, so HBM sees each population read once and
+// written once per step (ring and z-halo re-reads hit L2/MALL).  Every plane
+// is addressed through its own buffer descriptor (base = start of the plane
+// block, 64-bit, built on the scalar unit), so no 32-bit offset spans more
+// than one plane and domains of any size that fits the device are addressed.
 #include "lbm_kernels.h"
 
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 namespace hm {
@@ -132,12 +141,10 @@ struct BF16 : Half16 {
     {
         return __uint_as_float(static_cast<uint32_t>(v) << 16) * inv_scale;
     }
+    // round to nearest, ties to even (gfx950's v_cvt_pk_bf16_f32)
     static __device__ __forceinline__ E enc(T v, T scale)
     {
-        uint32_t u = __float_as_uint(v * scale);
-        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return static_cast<E>((u >> 16) | 0x40u);
-        u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
-        return static_cast<E>(u >> 16);
+        return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v * scale));
     }
     // Stochastic rounding with 16 random bits (v_cvt_sr_bf16_f32, the same
     // convention as the binary16 instruction).
@@ -173,11 +180,42 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t x)
     return x;
 }
 
+// Two 16-bit values of one (cell, direction) in one 32-bit word of the pair
+// layout: component 0 in the low half, component 1 in the high half.  Each
+// half is decoded and rounded exactly as a lone 16-bit value would be.
+template <typename ST>
+struct PairCodec {
+    static __device__ __forceinline__ float lo(uint32_t v, float inv_scale)
+    {
+        return ST::dec(static_cast<uint16_t>(v & 0xffffu), inv_scale);
+    }
+    static __device__ __forceinline__ float hi(uint32_t v, float inv_scale)
+    {
+        return ST::dec(static_cast<uint16_t>(v >> 16), inv_scale);
+    }
+    static __device__ __forceinline__ uint32_t enc(float a, float b, float scale)
+    {
+        if constexpr (std::is_same_v<ST, BF16>) {
+            const bf162_t h = {static_cast<__bf16>(a * scale), static_cast<__bf16>(b * scale)};
+            return __builtin_bit_cast(uint32_t, h);
+        } else {
+            const half2_t h = {static_cast<_Float16>(a * scale), static_cast<_Float16>(b * scale)};
+            return __builtin_bit_cast(uint32_t, h);
+        }
+    }
+    static __device__ __forceinline__ uint32_t enc_sr(float a, float b, float scale, uint32_t ra, uint32_t rb)
+    {
+        return static_cast<uint32_t>(ST::enc_sr(a, scale, ra)) | (static_cast<uint32_t>(ST::enc_sr(b, scale, rb)) << 16);
+    }
+};
+
 // Kernel parameters in the arithmetic type.
 template <typename T>
 struct Args {
     int nx, ny, nz;
-    int N;
+    int plane;   // nx * ny
+    int64_t N;   // cells
+    int pair;    // populations in the pair layout
     int zchunk, ntx, nty, nzc;
     T inv_tau[2], tau[2];
     T G_s, Gads_s[2];
@@ -197,7 +235,9 @@ static Args<T> make_args(const Problem& p)
 {
     Args<T> a{};
     a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
-    a.N = static_cast<int>(p.N);
+    a.plane = p.nx * p.ny;
+    a.N = p.N;
+    a.pair = pair_layout(p.storage, p.ncomp) ? 1 : 0;
     for (int s = 0; s < 2; ++s) {
         a.tau[s] = static_cast<T>(p.tau[s]);
         a.inv_tau[s] = static_cast<T>(1.0 / p.tau[s]);
@@ -219,6 +259,16 @@ static Args<T> make_args(const Problem& p)
         for (int s = 0; s < 2; ++s) a.res_dr[r][s] = static_cast<T>(p.res_rho[r][s] - p.rho0[s]);
     }
     return a;
+}
+
+// Element index of population (component s, direction i) of in-plane cell n of
+// plane z, in either layout (auxiliary kernels; the step kernels address whole
+// plane blocks through buffer descriptors).
+template <typename T>
+__device__ __forceinline__ size_t pidx(const Args<T>& a, int s, int i, int z, int64_t n)
+{
+    if (a.pair) return (((static_cast<size_t>(z) * kQ + i) * static_cast<size_t>(a.plane) + n) << 1) + s;
+    return ((static_cast<size_t>(s) * a.nz + z) * kQ + i) * static_cast<size_t>(a.plane) + n;
 }
 
 template <typename T>
@@ -256,52 +306,36 @@ __device__ __forceinline__ bool reservoir_dr(const Args<T>& a, int s, int x, int
     return in;
 }
 
+// Both components at once (pair kernel).
+template <typename T>
+__device__ __forceinline__ bool reservoir_dr2(const Args<T>& a, int x, int y, int z, T& dr0, T& dr1)
+{
+    bool in = false;
+    dr0 = T(0);
+    dr1 = T(0);
+#pragma unroll
+    for (int r = 0; r < kMaxRes; ++r) {
+        if (r < a.n_res) {
+            const int c = a.res_axis[r] == 0 ? x : (a.res_axis[r] == 1 ? y : z);
+            const bool hit = !in && c >= a.res_lo[r] && c < a.res_hi[r];
+            dr0 = hit ? a.res_dr[r][0] : dr0;
+            dr1 = hit ? a.res_dr[r][1] : dr1;
+            in = in || hit;
+        }
+    }
+    return in;
+}
+
 __device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrap_inc(int v, int n) { return v == n - 1 ? 0 : v + 1; }
 
-// Source index of the pull for direction i at cell (x,y,z): the cell x - c_i.
-// xs[0..2] = x+1, x, x-1 (index by 1 + c), same for rows and planes.
-struct PullIdx {
-    int col[3];   // x - c for c = -1, 0, +1  -> index c+1
-    int row[3];   // (y - c) * nx
-    int pln[3];   // (z - c) * nx * ny
-};
-
-__device__ __forceinline__ PullIdx pull_idx(int x, int y, int z, int nx, int ny, int nz)
-{
-    PullIdx q;
-    q.col[0] = wrap_inc(x, nx); q.col[1] = x; q.col[2] = wrap_dec(x, nx);
-    q.row[0] = wrap_inc(y, ny) * nx; q.row[1] = y * nx; q.row[2] = wrap_dec(y, ny) * nx;
-    const int plane = nx * ny;
-    q.pln[0] = wrap_inc(z, nz) * plane; q.pln[1] = z * plane; q.pln[2] = wrap_dec(z, nz) * plane;
-    return q;
-}
-
-// Fused step kernel.
-//
-// Addressing: the pull source of direction i at cell (x, y, z) is the cell
-// (x - cx, y - cy, z - cz).  Its plane part is uniform across the block, so it
-// is folded into a per-direction base pointer computed on the scalar unit; the
-// in-plane part takes one of nine values per thread, computed once before the
-// z sweep.  Loads are therefore "uniform base + 32-bit lane offset".
-template <typename E>
-__device__ __forceinline__ E ld_off(const E* base, uint32_t byte_off)
-{
-    return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
-template <typename E>
-__device__ __forceinline__ void st_off(E* base, uint32_t byte_off, E v)
-{
-    *reinterpret_cast<E*>(reinterpret_cast<char*>(base) + byte_off) = v;
-}
-
-// In-plane byte offsets of the nine (x - cx, y - cy) sources of a cell.
+// In-plane byte offsets of the nine (x - cx, y - cy) sources of a cell, for
+// elements of EB bytes.
 struct PlaneOffs {
     uint32_t o[3][3];  // [cy + 1][cx + 1]
 };
 
-template <typename E>
+template <int EB>
 __device__ __forceinline__ PlaneOffs plane_offs(int x, int y, int nx, int ny)
 {
     const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // x - c, c = -1, 0, 1
@@ -310,32 +344,30 @@ __device__ __forceinline__ PlaneOffs plane_offs(int x, int y, int nx, int ny)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) q.o[b][a] = static_cast<uint32_t>((ys[b] * nx + xs[a]) * static_cast<int>(sizeof(E)));
+        for (int a = 0; a < 3; ++a) q.o[b][a] = static_cast<uint32_t>(ys[b] * nx + xs[a]) * static_cast<uint32_t>(EB);
     return q;
 }
 
-// Pull the shifted pre-collision populations of one cell and component.
-// r covers the 19 direction arrays of component s; soff[c + 1] is the byte
-// offset of the source plane z - c; q holds the in-plane byte offsets.
-template <typename ST, typename T>
-__device__ __forceinline__ void pull(rsrc_t r, uint32_t dir_bytes, const uint32_t soff[3], const PlaneOffs& q,
-                                     T inv_scale, T h[kQ])
-{
-#pragma unroll
-    for (int i = 0; i < kQ; ++i)
-        h[i] = ST::dec(ST::bld(r, q.o[CY[i] + 1][CX[i] + 1], soff[CZ[i] + 1] + static_cast<uint32_t>(i) * dir_bytes),
-                       inv_scale);
-}
-
-// The same loads without decoding: the raw values can stay in flight while
-// other work runs, and are decoded where they are consumed.
+// Pull loads of one cell (raw stored values): direction i comes from the
+// source plane z - c_iz, whose block descriptor is r3[c_iz + 1], at the
+// in-plane offset of (x - c_ix, y - c_iy) plus i direction strides.
 template <typename ST>
-__device__ __forceinline__ void pull_raw(rsrc_t r, uint32_t dir_bytes, const uint32_t soff[3], const PlaneOffs& q,
+__device__ __forceinline__ void pull_raw(const rsrc_t r3[3], uint32_t dir_bytes, const PlaneOffs& q,
                                          typename ST::E e[kQ])
 {
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-        e[i] = ST::bld(r, q.o[CY[i] + 1][CX[i] + 1], soff[CZ[i] + 1] + static_cast<uint32_t>(i) * dir_bytes);
+        e[i] = ST::bld(r3[CZ[i] + 1], q.o[CY[i] + 1][CX[i] + 1], static_cast<uint32_t>(i) * dir_bytes);
+}
+
+template <typename ST, typename T>
+__device__ __forceinline__ void pull(const rsrc_t r3[3], uint32_t dir_bytes, const PlaneOffs& q, T inv_scale,
+                                     T h[kQ])
+{
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+        h[i] = ST::dec(ST::bld(r3[CZ[i] + 1], q.o[CY[i] + 1][CX[i] + 1], static_cast<uint32_t>(i) * dir_bytes),
+                       inv_scale);
 }
 
 template <typename T>
@@ -580,6 +612,88 @@ __device__ __forceinline__ void relax_dir_guo(const RelaxCoef<T>& k, const GuoCo
     post_o = k.ca * ho + (k.n * hi + (t - e));
 }
 
+// Both components of one cell (pair kernel): the equilibrium velocities of
+// Eq. (SC_u_eq) for s = 0 and 1, with the same expressions, in the same order,
+// as cell_velocity evaluates for each component, so a cell's result does not
+// depend on which kernel updated it.  The adhesion stencil of a single n_s
+// field is shared by the two components.
+template <int CNS, int LW, int LP>
+__device__ __forceinline__ void cell_velocity_pair(const Args<float>& a, int me, const float* rho_m,
+                                                   const float* rho_0, const float* rho_p, const float* ns_m,
+                                                   const float* ns_0, const float* ns_p, const float (&jc)[2][3],
+                                                   float ueq[2][3], float rho_own[2], float n[2])
+{
+    using T = float;
+    T rho = 0, den = 0, num[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T rc = rho_0[c * LP + me];
+        rho_own[c] = rc;
+        rho += rc;
+        den += rc * a.inv_tau[c];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) num[d] += jc[c][d] * a.inv_tau[c];
+    }
+    const T inv_den = den > T(0) ? recip(den) : T(0);
+    const T inv_rho = rho > T(0) ? recip(rho) : T(0);
+    T ga[CNS][3];
+#pragma unroll
+    for (int cn = 0; cn < CNS; ++cn) stencil<T, float, LW>(ns_m + cn * LP, ns_0 + cn * LP, ns_p + cn * LP, me, ga[cn]);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int cn = CNS == 2 ? s : 0;
+        T gi[3];
+        stencil<T, T, LW>(rho_m + (1 - s) * LP, rho_0 + (1 - s) * LP, rho_p + (1 - s) * LP, me, gi);
+        const bool present = rho_own[s] > T(0);
+        const T tau_s = a.tau[s], Gads = a.Gads_s[s];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T acc = -a.G_s * gi[d] - Gads * ga[cn][d] + a.F[d] * inv_rho;
+            ueq[s][d] = num[d] * inv_den + (present ? tau_s * acc : T(0));
+        }
+        n[s] = static_cast<T>(ns_0[cn * LP + me]);
+    }
+}
+
+// The GS-WBS for both components of one cell: u_macro of Eq. (HMCSC_u_macro)
+// and each component's total force, as cell_velocity_guo computes them.
+template <int CNS, int LW, int LP>
+__device__ __forceinline__ void cell_velocity_guo_pair(const Args<float>& a, int me, const float* rho_m,
+                                                       const float* rho_0, const float* rho_p, const float* ns_m,
+                                                       const float* ns_0, const float* ns_p,
+                                                       const float (&jc)[2][3], float um[3], float fo[2][3],
+                                                       float rho_own[2], float n_own[2])
+{
+    using T = float;
+    T rc[2], rho = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        rc[c] = rho_0[c * LP + me];
+        rho += rc[c];
+    }
+    const T inv_rho = rho > T(0) ? recip(rho) : T(0);
+    T m[3] = {0, 0, 0};
+    T ga[3];
+    if constexpr (CNS == 1) stencil<T, float, LW>(ns_m, ns_0, ns_p, me, ga);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int cn = CNS == 2 ? c : 0;
+        if constexpr (CNS == 2) stencil<T, float, LW>(ns_m + cn * LP, ns_0 + cn * LP, ns_p + cn * LP, me, ga);
+        T gi[3];
+        stencil<T, T, LW>(rho_m + (1 - c) * LP, rho_0 + (1 - c) * LP, rho_p + (1 - c) * LP, me, gi);
+        const T nc = static_cast<T>(ns_0[cn * LP + me]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            fo[c][d] = rc[c] * (-a.G_s * gi[d] - a.Gads_s[c] * ga[d] + a.F[d] * inv_rho);
+            m[d] += (T(1) - nc) * (jc[c][d] + T(0.5) * fo[c][d]);
+        }
+        rho_own[c] = rc[c];
+        n_own[c] = nc;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) um[d] = m[d] * inv_rho;
+}
+
 // One thread per (cell, component): a block of NC*TX*TY threads owns a TX x TY
 // column of cells; threads [s*TX*TY, (s+1)*TX*TY) handle component s.  The two
 // components of a cell meet only through LDS (densities and first moments),
@@ -653,8 +767,8 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     // a ragged tile edge duplicates the last active lane of its row/column
     const int me = (y - y0 + 1) * LW + (x - x0 + 1);
     const int tj = (y - y0) * TX + (x - x0);
-    const PlaneOffs qme = plane_offs<E>(x, y, a.nx, a.ny);
-    const uint32_t own = static_cast<uint32_t>((y * a.nx + x) * static_cast<int>(sizeof(E)));
+    const PlaneOffs qme = plane_offs<sizeof(E)>(x, y, a.nx, a.ny);
+    const uint32_t own = static_cast<uint32_t>(y * a.nx + x) * static_cast<uint32_t>(sizeof(E));
 
     // ring cell of this thread (if any): top row, bottom row, left, right column
     const int ring_n = 2 * (TXe + 2) + 2 * TYe;
@@ -670,7 +784,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     const int rx = ((x0 + rlx) % a.nx + a.nx) % a.nx;
     const int ry = ((y0 + rly) % a.ny + a.ny) % a.ny;
     const int rme = (rly + 1) * LW + (rlx + 1);
-    const PlaneOffs qring = plane_offs<E>(rx, ry, a.nx, a.ny);
+    const PlaneOffs qring = plane_offs<sizeof(E)>(rx, ry, a.nx, a.ny);
 
     // n_s cells staged by this thread: LDS index and in-plane offset
     const int nsw = TXe + 2, nsh = TYe + 2;
@@ -693,18 +807,21 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     auto wrapz = [&](int p) { return p < 0 ? p + a.nz : (p >= a.nz ? p - a.nz : p); };
     const uint32_t t_key = fmix32(t ^ kGolden);  // stochastic rounding: time part of the counter
 
-    const uint32_t dir_bytes = static_cast<uint32_t>(a.N * static_cast<int>(sizeof(E)));
-    const uint32_t plane_bytes = static_cast<uint32_t>(plane * static_cast<int>(sizeof(E)));
-    // one buffer descriptor per component spans its 19 direction arrays
-    const uint32_t comp_bytes = static_cast<uint32_t>(kQ) * dir_bytes;
-    const rsrc_t ra = make_rsrc(A + static_cast<size_t>(s * kQ) * static_cast<size_t>(a.N), comp_bytes);
-    const rsrc_t rb = make_rsrc(B + static_cast<size_t>(s * kQ) * static_cast<size_t>(a.N), comp_bytes);
+    // The 19 direction arrays of one plane of this component form a block;
+    // each plane block is addressed through its own buffer descriptor (64-bit
+    // base on the scalar unit, 32-bit offsets within the block).
+    const size_t cstride = static_cast<size_t>(a.nz) * kQ * static_cast<size_t>(plane);
+    const E* Ac = A + static_cast<size_t>(s) * cstride;
+    E* Bc = B + static_cast<size_t>(s) * cstride;
+    const uint32_t dir_bytes = static_cast<uint32_t>(plane) * static_cast<uint32_t>(sizeof(E));
+    const uint32_t blk_bytes = static_cast<uint32_t>(kQ) * dir_bytes;
+    auto blk = [&](const E* base, int p) {
+        return make_rsrc(base + static_cast<size_t>(p) * kQ * static_cast<size_t>(plane), blk_bytes);
+    };
 
     auto pull_plane = [&](int p, const PlaneOffs& q, T h[kQ]) {
-        const uint32_t so[3] = {static_cast<uint32_t>(wrapz(p + 1)) * plane_bytes,  // c_z = -1
-                                static_cast<uint32_t>(p) * plane_bytes,
-                                static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};  // c_z = +1
-        pull<ST, T>(ra, dir_bytes, so, q, a.inv_scale, h);
+        const rsrc_t r3[3] = {blk(Ac, wrapz(p + 1)), blk(Ac, p), blk(Ac, wrapz(p - 1))};  // c_z = -1, 0, +1
+        pull<ST, T>(r3, dir_bytes, q, a.inv_scale, h);
     };
     // A select per value rather than a per-lane branch: in divergent control
     // flow a branch makes the compiler merge the two versions of all 19
@@ -774,7 +891,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
         else
             cell_velocity<T, NC, CNS, LW, LP>(a, s, me, &s_rho[sm][0][0], &s_rho[s0][0][0], &s_rho[sp][0][0],
                                               &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, ueq, rho_own, n);
-        const uint32_t zo = static_cast<uint32_t>(z) * plane_bytes;
+        const rsrc_t rz = blk(Bc, z);
         const RelaxCoef<T> k = relax_coef<T>(a, s, rho_own, ueq, n);
         GuoCoef<T> g{};
         if constexpr (FS == kForcingGuo) g = guo_coef<T>(a, s, n, fo, ueq);
@@ -790,25 +907,25 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
             // counter: (cell, component) mixed with the time step, then the direction
             // 32 random bits per direction pair (i, i+9), 16 for each value:
             // fmix32 of (cell, component, time), then xorshift32 steps
-            const uint32_t cell = static_cast<uint32_t>(z * plane + y * a.nx + x);
+            const uint32_t cell = static_cast<uint32_t>(z) * static_cast<uint32_t>(plane) + static_cast<uint32_t>(y * a.nx + x);
             uint32_t r = fmix32(t_key ^ (2u * cell + static_cast<uint32_t>(s))) | 1u;  // nonzero state
-            ST::bst(ST::enc_sr(rest(), a.scale, r >> 16), rb, own, zo);
+            ST::bst(ST::enc_sr(rest(), a.scale, r >> 16), rz, own, 0u);
 #pragma unroll
             for (int i = 1; i <= 9; ++i) {
                 T pi, po;
                 pair(i, pi, po);
                 r = xorshift32(r);
-                ST::bst(ST::enc_sr(pi, a.scale, r & 0xffffu), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
-                ST::bst(ST::enc_sr(po, a.scale, r >> 16), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
+                ST::bst(ST::enc_sr(pi, a.scale, r & 0xffffu), rz, own, static_cast<uint32_t>(i) * dir_bytes);
+                ST::bst(ST::enc_sr(po, a.scale, r >> 16), rz, own, static_cast<uint32_t>(i + 9) * dir_bytes);
             }
         } else {
-            ST::bst(ST::enc(rest(), a.scale), rb, own, zo);
+            ST::bst(ST::enc(rest(), a.scale), rz, own, 0u);
 #pragma unroll
             for (int i = 1; i <= 9; ++i) {
                 T pi, po;
                 pair(i, pi, po);
-                ST::bst(ST::enc(pi, a.scale), rb, own, zo + static_cast<uint32_t>(i) * dir_bytes);
-                ST::bst(ST::enc(po, a.scale), rb, own, zo + static_cast<uint32_t>(i + 9) * dir_bytes);
+                ST::bst(ST::enc(pi, a.scale), rz, own, static_cast<uint32_t>(i) * dir_bytes);
+                ST::bst(ST::enc(po, a.scale), rz, own, static_cast<uint32_t>(i + 9) * dir_bytes);
             }
         }
     };
@@ -830,18 +947,12 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
         // kept in flight.  So nothing here touches memory conditionally:
         // lanes beyond a ragged tile edge duplicate an active lane (same
         // cell, same LDS slots, identical values written twice), lanes
-        // without a ring cell load at offsets past the buffer's range
-        // (dropped by the range check), and lanes without an n_s cell
+        // without a ring cell load the tile's last ring cell (a cell of the
+        // domain; the values are not used), and lanes without an n_s cell
         // duplicate cell 0 of the staging list.
         constexpr int NT_ = TileShared<ST, NC, CNS, TX, TY>::NT;
-        constexpr uint32_t kOff = 0x80000000u;  // beyond any buffer of a single component below 2 GiB
         T* hs = &sh.hs[0][0] + threadIdx.x;
-        PlaneOffs qr = qring;
-        if (!ring)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) qr.o[b][c] |= kOff;
+        const PlaneOffs& qr = qring;
         // list cell 0 is the corner (x0 - 1, y0 - 1), LDS index 0
         const int ns_off0 = (((y0 - 1) % a.ny + a.ny) % a.ny) * a.nx + ((x0 - 1) % a.nx + a.nx) % a.nx;
         int nl[NSMAX], no[NSMAX];
@@ -851,10 +962,8 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
             no[k] = ns_lds[k] >= 0 ? ns_off[k] : ns_off0;
         }
         auto issue = [&](int p, const PlaneOffs& q, E e[kQ]) {
-            const uint32_t so[3] = {static_cast<uint32_t>(wrapz(p + 1)) * plane_bytes,
-                                    static_cast<uint32_t>(p) * plane_bytes,
-                                    static_cast<uint32_t>(wrapz(p - 1)) * plane_bytes};
-            pull_raw<ST>(ra, dir_bytes, so, q, e);
+            const rsrc_t r3[3] = {blk(Ac, wrapz(p + 1)), blk(Ac, p), blk(Ac, wrapz(p - 1))};
+            pull_raw<ST>(r3, dir_bytes, q, e);
         };
         if constexpr (ONE) {
             // One cell deep (the instance launched for nz = 1): planes z - 1,
@@ -1078,23 +1187,395 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
     }
 }
 
-template <typename ST, int NC, int CNS, int TX, int TY, int FS, bool ONE>
-__global__ __launch_bounds__(NC* TX* TY) void k_step(Args<typename ST::T> a,
-                                                      const typename ST::E* __restrict__ A,
-                                                      typename ST::E* __restrict__ B,
-                                                      const float* __restrict__ ns)
+// ---------------------------------------------------------------------------
+// Pair kernel: two components in a 16-bit format, one thread per cell.
+//
+// In the pair layout one 32-bit word holds both components' value of one
+// (cell, direction), so a thread pulls its cell's 38 populations with 19
+// 4-byte loads and stores them with 19 4-byte stores.  Per memory operation
+// that moves twice the bytes of a lone 16-bit value, which doubles the bytes
+// a wave keeps in flight under the same limit on outstanding operations (the
+// limit that bounds a 16-bit kernel with one value per lane).  The two
+// components of a cell meet in registers, so the first moments need no LDS
+// exchange; the densities still go to LDS for the force stencils.
+//
+// The waves of a block have fixed roles.  The first TX*TY threads own one
+// cell each: they pull, collide and store it, with the next plane's loads in
+// flight.  The last NR threads (whole waves) stage the one-cell ring of
+// densities around the tile and the n_s planes: they hold no collision state,
+// so the cell waves keep their registers for the prefetch.
+//
+// LDS: four density / n_s plane slots (plane p in slot p mod 4, one barrier
+// per plane) and the raw words of the plane staged last, private to each cell
+// thread.
+template <int CNS, int TX, int TY>
+struct PairShared {
+    static constexpr int LW = TX + 2;
+    static constexpr int LP = LW * (TY + 2);
+    static constexpr int NT = TX * TY;
+    float rho[4][2][LP];
+    float ns[4][CNS][LP];
+    uint32_t hs[kQ][NT];
+};
+
+constexpr int kPairRing = 192;  // ring / n_s threads per block (three waves)
+
+// Planes a cell wave keeps in flight ahead of the one it stages (1 or 2).
+#ifndef LBM_PAIR_AHEAD
+#define LBM_PAIR_AHEAD 1
+#endif
+
+template <typename ST, int CNS, int TX, int TY, int FS, bool ONE = false>
+__device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint32_t* __restrict__ A,
+                                               uint32_t* __restrict__ B, const float* __restrict__ ns, int L,
+                                               uint32_t t, PairShared<CNS, TX, TY>& sh)
 {
-    __shared__ TileShared<ST, NC, CNS, TX, TY> sh;
+    using T = float;
+    using PC = PairCodec<ST>;
+    constexpr int LW = TX + 2;
+    constexpr int LP = LW * (TY + 2);
+    constexpr int NT = TX * TY;
+    constexpr int NR = kPairRing;
+    constexpr int NSR = (LP + NR - 1) / NR;  // n_s cells staged per ring thread and plane
+    static_assert(NT % 64 == 0, "the roles must fill whole waves");
+    static_assert(2 * (TX + 2) + 2 * TY <= NR, "one ring cell per ring thread");
+    auto& s_rho = sh.rho;
+    auto& s_ns = sh.ns;
+
+    const int tx = L % a.ntx;
+    const int ty = (L / a.ntx) % a.nty;
+    const int tz = L / (a.ntx * a.nty);
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int zs = tz * a.zchunk;
+    const int ze = min(zs + a.zchunk, a.nz);
+    const int TXe = min(TX, a.nx - x0);
+    const int TYe = min(TY, a.ny - y0);
+    const int plane = a.plane;
+    const int tl = static_cast<int>(threadIdx.x);
+
+    auto wrapz = [&](int p) { return p < 0 ? p + a.nz : (p >= a.nz ? p - a.nz : p); };
+    // one buffer descriptor per plane block of 19 direction arrays of words
+    const uint32_t dir_bytes = static_cast<uint32_t>(plane) * 4u;
+    const uint32_t blk_bytes = static_cast<uint32_t>(kQ) * dir_bytes;
+    auto blk = [&](const uint32_t* base, int p) {
+        return make_rsrc(base + static_cast<size_t>(p) * kQ * static_cast<size_t>(plane), blk_bytes);
+    };
+    auto issue = [&](int p, const PlaneOffs& q, uint32_t e[kQ]) {
+        const rsrc_t r3[3] = {blk(A, wrapz(p + 1)), blk(A, p), blk(A, wrapz(p - 1))};  // c_z = -1, 0, +1
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            e[i] = __builtin_amdgcn_raw_buffer_load_b32(r3[CZ[i] + 1], q.o[CY[i] + 1][CX[i] + 1],
+                                                        static_cast<uint32_t>(i) * dir_bytes, 0);
+    };
+    // densities rho_0, rho_1 of a cell from its raw words, with the Dirichlet
+    // density of a reservoir cell (a select per value, skipped as a whole when
+    // no lane of the wave is in a reservoir)
+    auto densities = [&](int cx, int cy, int cz, const uint32_t e[kQ], T& r0, T& r1) {
+        T h0[kQ], h1[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            h0[i] = PC::lo(e[i], a.inv_scale);
+            h1[i] = PC::hi(e[i], a.inv_scale);
+        }
+        T dr0, dr1;
+        const bool in = reservoir_dr2(a, cx, cy, cz, dr0, dr1);
+        if (__builtin_amdgcn_ballot_w64(in) != 0) {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                h0[i] = in ? wgt<T>(i) * dr0 : h0[i];
+                h1[i] = in ? wgt<T>(i) * dr1 : h1[i];
+            }
+        }
+        r0 = a.rho0[0] + sum19(h0);
+        r1 = a.rho0[1] + sum19(h1);
+    };
+    auto rslot = [&](int p) { return (p - zs + 1) & 3; };
+
+    if (tl >= NT) {
+        // ---- ring / n_s waves ----
+        const int r = tl - NT;
+        const int ring_n = 2 * (TXe + 2) + 2 * TYe;
+        const bool ring = r < ring_n;
+        int rlx, rly;
+        {
+            const int q = min(r, ring_n - 1);  // threads past the ring repeat its last cell
+            if (q < TXe + 2) { rlx = q - 1; rly = -1; }
+            else if (q < 2 * (TXe + 2)) { rlx = q - (TXe + 2) - 1; rly = TYe; }
+            else if (q < 2 * (TXe + 2) + TYe) { rlx = -1; rly = q - 2 * (TXe + 2); }
+            else { rlx = TXe; rly = q - 2 * (TXe + 2) - TYe; }
+        }
+        const int rx = ((x0 + rlx) % a.nx + a.nx) % a.nx;
+        const int ry = ((y0 + rly) % a.ny + a.ny) % a.ny;
+        const int rme = (rly + 1) * LW + (rlx + 1);
+        const PlaneOffs qring = plane_offs<4>(rx, ry, a.nx, a.ny);
+        // n_s cells of this thread (LDS index, in-plane index); past the list
+        // a thread repeats its first cell, the corner (x0 - 1, y0 - 1)
+        const int nsw = TXe + 2, nsh = TYe + 2;
+        const int ns_off0 = (((y0 - 1) % a.ny + a.ny) % a.ny) * a.nx + ((x0 - 1) % a.nx + a.nx) % a.nx;
+        int nl[NSR], no[NSR];
+#pragma unroll
+        for (int k = 0; k < NSR; ++k) {
+            const int c = r + k * NR;
+            if (c < nsw * nsh) {
+                const int llx = c % nsw - 1, lly = c / nsw - 1;
+                const int gx = ((x0 + llx) % a.nx + a.nx) % a.nx;
+                const int gy = ((y0 + lly) % a.ny + a.ny) % a.ny;
+                nl[k] = (lly + 1) * LW + llx + 1;
+                no[k] = gy * a.nx + gx;
+            } else {
+                nl[k] = 0;
+                no[k] = ns_off0;
+            }
+        }
+        uint32_t er[kQ];
+        float nsv[NSR][CNS];
+        auto issue_ring = [&](int p) {
+            issue(p, qring, er);
+            const float* nsp = ns + static_cast<size_t>(p) * static_cast<size_t>(plane);
+#pragma unroll
+            for (int k = 0; k < NSR; ++k)
+#pragma unroll
+                for (int c = 0; c < CNS; ++c) nsv[k][c] = nsp[static_cast<size_t>(c) * a.N + no[k]];
+        };
+        // consume the loads of plane p into LDS slot `slot`
+        auto consume_ring = [&](int p, int slot) {
+            T r0, r1;
+            densities(rx, ry, p, er, r0, r1);
+            if (ring) {
+                s_rho[slot][0][rme] = r0;
+                s_rho[slot][1][rme] = r1;
+            }
+#pragma unroll
+            for (int k = 0; k < NSR; ++k)
+#pragma unroll
+                for (int c = 0; c < CNS; ++c) s_ns[slot][c][nl[k]] = nsv[k][c];
+        };
+        // ... then issue those of plane pn (unconditionally, so the waits stay
+        // exact)
+        auto stage_ring = [&](int p, int slot, int pn) {
+            consume_ring(p, slot);
+            __builtin_amdgcn_sched_barrier(0);
+            issue_ring(pn);
+        };
+        if constexpr (ONE) {
+            issue_ring(0);
+            consume_ring(0, rslot(0));
+            __syncthreads();
+            return;
+        } else {
+            auto next = [&](int p) { return wrapz(p + 1 <= ze ? p + 1 : ze); };
+            issue_ring(wrapz(zs - 1));
+            stage_ring(wrapz(zs - 1), rslot(zs - 1), zs);
+            stage_ring(zs, rslot(zs), next(zs));
+            for (int z = zs; z < ze; ++z) {
+                stage_ring(wrapz(z + 1), rslot(z + 1), next(z + 1));
+                __syncthreads();
+            }
+            return;
+        }
+    }
+
+    // ---- cell waves ----
+    const int lx = tl % TX;
+    const int ly = tl / TX;
+    // a lane beyond a ragged tile edge duplicates the last active lane of its
+    // row / column (same cell, same LDS slots, identical values written twice)
+    const int x = x0 + min(lx, TXe - 1);
+    const int y = y0 + min(ly, TYe - 1);
+    const int me = (y - y0 + 1) * LW + (x - x0 + 1);
+    const PlaneOffs qme = plane_offs<4>(x, y, a.nx, a.ny);
+    const uint32_t own = static_cast<uint32_t>(y * a.nx + x) * 4u;
+    const uint32_t t_key = fmix32(t ^ kGolden);  // stochastic rounding: time part of the counter
+
+    // Collision of plane z from the raw words hz of the own cell and the LDS
+    // slots of planes z-1, z, z+1.  The words are decoded where they are used
+    // (twice: first moments, then the relaxation) rather than held as 38
+    // floats.
+    auto collide = [&](int z, int sm, int s0, int sp, const uint32_t hz[kQ]) {
+        T dr0, dr1;
+        const bool in = reservoir_dr2(a, x, y, z, dr0, dr1);
+        uint32_t w[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) w[i] = hz[i];
+        auto h0 = [&](int i) { return in ? wgt<T>(i) * dr0 : PC::lo(w[i], a.inv_scale); };
+        auto h1 = [&](int i) { return in ? wgt<T>(i) * dr1 : PC::hi(w[i], a.inv_scale); };
+        T jc[2][3];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            T j3[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int i = 1; i <= 9; ++i) {
+                const T hi_ = c == 0 ? h0(i) : h1(i), ho_ = c == 0 ? h0(i + 9) : h1(i + 9);
+                if (CX[i]) j3[0] += CX[i] > 0 ? hi_ - ho_ : ho_ - hi_;
+                if (CY[i]) j3[1] += CY[i] > 0 ? hi_ - ho_ : ho_ - hi_;
+                if (CZ[i]) j3[2] += CZ[i] > 0 ? hi_ - ho_ : ho_ - hi_;
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) jc[c][d] = j3[d];
+        }
+        T ueq[2][3], rho_own[2], n[2], fo[2][3];
+        if constexpr (FS == kForcingGuo) {
+            T um[3];
+            cell_velocity_guo_pair<CNS, LW, LP>(a, me, &s_rho[sm][0][0], &s_rho[s0][0][0], &s_rho[sp][0][0],
+                                                &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, um, fo,
+                                                rho_own, n);
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ueq[c][d] = um[d];
+        } else {
+            cell_velocity_pair<CNS, LW, LP>(a, me, &s_rho[sm][0][0], &s_rho[s0][0][0], &s_rho[sp][0][0],
+                                            &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, ueq, rho_own, n);
+        }
+        // an empty asm that claims to change the words: the decodes below are
+        // then not merged with those of the first moments (which would keep
+        // all 38 decoded values live across the velocity computation)
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) asm volatile("" : "+v"(w[i]));
+        const RelaxCoef<T> k0 = relax_coef<T>(a, 0, rho_own[0], ueq[0], n[0]);
+        const RelaxCoef<T> k1 = relax_coef<T>(a, 1, rho_own[1], ueq[1], n[1]);
+        GuoCoef<T> g0{}, g1{};
+        if constexpr (FS == kForcingGuo) {
+            g0 = guo_coef<T>(a, 0, n[0], fo[0], ueq[0]);
+            g1 = guo_coef<T>(a, 1, n[1], fo[1], ueq[1]);
+        }
+        auto rest = [&](const RelaxCoef<T>& k, const GuoCoef<T>& g, T h) {
+            if constexpr (FS == kForcingGuo) return relax_rest_guo(k, g, h);
+            else return relax_rest(k, h);
+        };
+        auto pairdir = [&](const RelaxCoef<T>& k, const GuoCoef<T>& g, int i, T hi_, T ho_, T& pi, T& po) {
+            if constexpr (FS == kForcingGuo) relax_dir_guo(k, g, i, hi_, ho_, pi, po);
+            else relax_dir(k, i, hi_, ho_, pi, po);
+        };
+        const rsrc_t rz = blk(B, z);
+        if (a.sr) {
+            // the random streams of the split kernels: per (cell, component)
+            // fmix32 of the counter, then one xorshift32 step per direction pair
+            const uint32_t cell = static_cast<uint32_t>(z) * static_cast<uint32_t>(plane) + static_cast<uint32_t>(y * a.nx + x);
+            uint32_t r0 = fmix32(t_key ^ (2u * cell)) | 1u;
+            uint32_t r1 = fmix32(t_key ^ (2u * cell + 1u)) | 1u;
+            __builtin_amdgcn_raw_buffer_store_b32(
+                PC::enc_sr(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), a.scale, r0 >> 16, r1 >> 16), rz, own, 0u, kNT);
+#pragma unroll
+            for (int i = 1; i <= 9; ++i) {
+                T pi0, po0, pi1, po1;
+                pairdir(k0, g0, i, h0(i), h0(i + 9), pi0, po0);
+                pairdir(k1, g1, i, h1(i), h1(i + 9), pi1, po1);
+                r0 = xorshift32(r0);
+                r1 = xorshift32(r1);
+                __builtin_amdgcn_raw_buffer_store_b32(PC::enc_sr(pi0, pi1, a.scale, r0 & 0xffffu, r1 & 0xffffu), rz,
+                                                      own, static_cast<uint32_t>(i) * dir_bytes, kNT);
+                __builtin_amdgcn_raw_buffer_store_b32(PC::enc_sr(po0, po1, a.scale, r0 >> 16, r1 >> 16), rz, own,
+                                                      static_cast<uint32_t>(i + 9) * dir_bytes, kNT);
+            }
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(PC::enc(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), a.scale), rz, own,
+                                                  0u, kNT);
+#pragma unroll
+            for (int i = 1; i <= 9; ++i) {
+                T pi0, po0, pi1, po1;
+                pairdir(k0, g0, i, h0(i), h0(i + 9), pi0, po0);
+                pairdir(k1, g1, i, h1(i), h1(i + 9), pi1, po1);
+                __builtin_amdgcn_raw_buffer_store_b32(PC::enc(pi0, pi1, a.scale), rz, own,
+                                                      static_cast<uint32_t>(i) * dir_bytes, kNT);
+                __builtin_amdgcn_raw_buffer_store_b32(PC::enc(po0, po1, a.scale), rz, own,
+                                                      static_cast<uint32_t>(i + 9) * dir_bytes, kNT);
+            }
+        }
+    };
+
+    if constexpr (ONE) {
+        // One cell deep: planes z - 1, z and z + 1 are all plane 0, staged
+        // once and collided against itself.
+        const int slot = rslot(0);
+        uint32_t r1[kQ];
+        issue(0, qme, r1);
+        T d0, d1;
+        densities(x, y, 0, r1, d0, d1);
+        s_rho[slot][0][me] = d0;
+        s_rho[slot][1][me] = d1;
+        __syncthreads();
+        collide(0, slot, slot, slot, r1);
+        return;
+    } else {
+        // Three planes at a time, as in the split kernel: plane z is collided
+        // from registers, plane z+1 waits in LDS (hs), and the loads of plane
+        // z+1+AHEAD are in flight over the barrier and the collision.  No
+        // memory access in the sweep is conditional (a skipped access would
+        // make the compiler's waits drain the loads kept in flight).
+        constexpr int AHEAD = LBM_PAIR_AHEAD;
+        constexpr bool DEEP = AHEAD == 2;
+        uint32_t* hsp = &sh.hs[0][0] + tl;
+        uint32_t rA[kQ];
+        uint32_t rB[DEEP ? kQ : 1];
+        // Stage plane p, whose loads are in rc: its densities go to LDS and its
+        // words to hs, whose previous content (the plane before) moves to hz;
+        // then the loads of plane pn are issued into rc.
+        auto stage_pipe = [&](int p, int slot, int pn, uint32_t hz[kQ], uint32_t rc[kQ]) {
+            T d0, d1;
+            densities(x, y, p, rc, d0, d1);
+            s_rho[slot][0][me] = d0;
+            s_rho[slot][1][me] = d1;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                hz[i] = hsp[i * NT];
+                hsp[i * NT] = rc[i];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            issue(pn, qme, rc);
+        };
+        // the plane whose loads a stage of plane p issues: p + AHEAD, or after
+        // the last plane one already staged again (cache hits)
+        auto ahead = [&](int p) { return wrapz(p + AHEAD <= ze ? p + AHEAD : ze); };
+        uint32_t (&r_odd)[kQ] = rA;
+        uint32_t (&r_even)[kQ] = *reinterpret_cast<uint32_t(*)[kQ]>(DEEP ? static_cast<uint32_t*>(rB) : static_cast<uint32_t*>(rA));
+        uint32_t hz[kQ];
+        // prologue: planes zs-1 (densities only) and zs (to hs)
+        issue(wrapz(zs - 1), qme, r_odd);
+        if constexpr (DEEP) issue(zs, qme, r_even);
+        stage_pipe(wrapz(zs - 1), rslot(zs - 1), ahead(zs - 1), hz, r_odd);
+        stage_pipe(zs, rslot(zs), ahead(zs), hz, r_even);
+        // unrolled by two so the register sets keep fixed names
+        for (int z = zs; z < ze; z += 2) {
+            stage_pipe(wrapz(z + 1), rslot(z + 1), ahead(z + 1), hz, r_odd);
+            __syncthreads();
+            collide(z, rslot(z - 1), rslot(z), rslot(z + 1), hz);
+            if (z + 1 >= ze) break;
+            stage_pipe(wrapz(z + 2), rslot(z + 2), ahead(z + 2), hz, r_even);
+            __syncthreads();
+            collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), hz);
+        }
+    }
+}
+
+// Two components in a 16-bit format use the pair layout and kernel.
+template <typename ST, int NC>
+constexpr bool kPair = sizeof(typename ST::E) == 2 && NC == 2;
+
+template <typename ST, int NC, int TX, int TY>
+constexpr int kThreads = kPair<ST, NC> ? TX * TY + kPairRing : NC * TX * TY;
+
+template <typename ST, int NC, int CNS, int TX, int TY, int FS, bool ONE>
+__global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step(Args<typename ST::T> a,
+                                                                    const typename ST::E* __restrict__ A,
+                                                                    typename ST::E* __restrict__ B,
+                                                                    const float* __restrict__ ns)
+{
     // XCD-aware tile order: blocks are dispatched round-robin over 8 XCDs, so
     // give each XCD a contiguous run of tiles (neighbours share its L2).
     const int nb = gridDim.x;
     int L = blockIdx.x;
     if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    step_tile<ST, NC, CNS, TX, TY, FS, ONE>(a, A, B, ns, L, a.t, sh);
+    if constexpr (kPair<ST, NC>) {
+        __shared__ PairShared<CNS, TX, TY> sh;
+        step_tile_pair<ST, CNS, TX, TY, FS, ONE>(a, reinterpret_cast<const uint32_t*>(A), reinterpret_cast<uint32_t*>(B),
+                                                 ns, L, a.t, sh);
+    } else {
+        __shared__ TileShared<ST, NC, CNS, TX, TY> sh;
+        step_tile<ST, NC, CNS, TX, TY, FS, ONE>(a, A, B, ns, L, a.t, sh);
+    }
 }
 
-
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Batched step: the tiles of many domains in one launch.  The device table
 // holds a header and one entry per domain (geometry, parameters, ping-pong
@@ -1122,11 +1603,10 @@ struct BatchHeader {
 constexpr size_t kBatchEntryOffset = 64;
 
 template <typename ST, int NC, int CNS, int TX, int TY>
-__global__ __launch_bounds__(NC* TX* TY) void k_step_batch(const char* __restrict__ table, int k)
+__global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step_batch(const char* __restrict__ table, int k)
 {
     using T = typename ST::T;
     using E = typename ST::E;
-    __shared__ TileShared<ST, NC, CNS, TX, TY> sh;
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(table);
     const BatchEntry<T>* ent = reinterpret_cast<const BatchEntry<T>*>(table + kBatchEntryOffset);
     const int total = hdr->total_tiles;
@@ -1136,6 +1616,8 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step_batch(const char* __restric
     // (neighbouring tiles re-read each other's edge cells through its L2)
     const int nb = gridDim.x;
     const int b0 = (nb & 7) == 0 ? (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    using Shared = std::conditional_t<kPair<ST, NC>, PairShared<CNS, TX, TY>, TileShared<ST, NC, CNS, TX, TY>>;
+    __shared__ Shared sh;
     for (int w = b0; w < total; w += nb) {
         int lo = 0, hi = nd - 1;  // last domain with tile_begin <= w
         while (lo < hi) {
@@ -1147,34 +1629,82 @@ __global__ __launch_bounds__(NC* TX* TY) void k_step_batch(const char* __restric
         if (k >= e.steps) continue;
         const int cur = (e.parity + k) & 1;
         __syncthreads();  // the previous tile's LDS is no longer read
-        step_tile<ST, NC, CNS, TX, TY, kForcingShanChen>(e.a, static_cast<const E*>(e.buf[cur]), static_cast<E*>(const_cast<void*>(e.buf[1 - cur])),
-                                       e.ns, w - e.tile_begin, e.a.t + static_cast<uint32_t>(k), sh);
+        if constexpr (kPair<ST, NC>)
+            step_tile_pair<ST, CNS, TX, TY, kForcingShanChen>(e.a, static_cast<const uint32_t*>(e.buf[cur]),
+                                                              static_cast<uint32_t*>(const_cast<void*>(e.buf[1 - cur])),
+                                                              e.ns, w - e.tile_begin, e.a.t + static_cast<uint32_t>(k), sh);
+        else
+            step_tile<ST, NC, CNS, TX, TY, kForcingShanChen>(e.a, static_cast<const E*>(e.buf[cur]),
+                                                             static_cast<E*>(const_cast<void*>(e.buf[1 - cur])), e.ns,
+                                                             w - e.tile_begin, e.a.t + static_cast<uint32_t>(k), sh);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Auxiliary kernels (initialisation, checkpoints, FP64 diagnostics).  They run
-// once per call, not per step, so they use a plain one-thread-per-cell grid.
+// once per call, not per step: plain grid-stride loops over the cells.
+
+#define CELL_LOOP(n, N)                                                                                      \
+    for (int64_t n = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; n < (N);                  \
+         n += static_cast<int64_t>(gridDim.x) * blockDim.x)
+
+struct Cell {
+    int x, y, z, ip;  // coordinates and in-plane index
+};
+
+template <typename T>
+__device__ __forceinline__ Cell cell_of(const Args<T>& a, int64_t n)
+{
+    Cell c;
+    c.z = static_cast<int>(n / a.plane);
+    c.ip = static_cast<int>(n - static_cast<int64_t>(c.z) * a.plane);
+    c.x = c.ip % a.nx;
+    c.y = c.ip / a.nx;
+    return c;
+}
+
+template <typename T>
+__device__ __forceinline__ int64_t cell_at(const Args<T>& a, int x, int y, int z)
+{
+    return static_cast<int64_t>(z) * a.plane + y * a.nx + x;
+}
+
+// direction i as (cx, cy, cz, w_i) for a runtime i
+template <typename T>
+__device__ __forceinline__ void dir_of(int i, int& dx, int& dy, int& dz, T& w)
+{
+    dx = dy = dz = 0;
+    w = T(0);
+#pragma unroll
+    for (int k = 0; k < kQ; ++k)
+        if (k == i) {
+            dx = CX[k];
+            dy = CY[k];
+            dz = CZ[k];
+            w = wgt<T>(k);
+        }
+}
 
 template <typename ST>
 __global__ void k_init(Args<typename ST::T> a, int ncomp, const double* __restrict__ rho_init,
                        typename ST::E* __restrict__ A)
 {
     using T = typename ST::T;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-    const int x = n % a.nx, y = (n / a.nx) % a.ny, z = n / (a.nx * a.ny);
-    // A_i(y) must hold f_i(y + c_i, 0) (pull storage)
-    for (int s = 0; s < ncomp; ++s) {
+    CELL_LOOP(n, a.N)
+    {
+        const Cell c = cell_of(a, n);
+        // A_i(y) must hold f_i(y + c_i, 0) (pull storage)
+        for (int s = 0; s < ncomp; ++s) {
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            const int xd = (x + CX[i] + a.nx) % a.nx, yd = (y + CY[i] + a.ny) % a.ny, zd = (z + CZ[i] + a.nz) % a.nz;
-            const int d = (zd * a.ny + yd) * a.nx + xd;
-            const int res = reservoir_of(a, xd, yd, zd);
-            const double rho = res >= 0 ? static_cast<double>(a.res_dr[res][s]) + static_cast<double>(a.rho0[s])
-                                        : rho_init[static_cast<size_t>(s) * a.N + d];
-            const double h = wgt<double>(i) * (rho - static_cast<double>(a.rho0[s]));
-            A[static_cast<size_t>(s * kQ + i) * a.N + n] = ST::enc(static_cast<T>(h), a.scale);
+            for (int i = 0; i < kQ; ++i) {
+                const int xd = (c.x + CX[i] + a.nx) % a.nx, yd = (c.y + CY[i] + a.ny) % a.ny,
+                          zd = (c.z + CZ[i] + a.nz) % a.nz;
+                const int res = reservoir_of(a, xd, yd, zd);
+                const double rho = res >= 0 ? static_cast<double>(a.res_dr[res][s]) + static_cast<double>(a.rho0[s])
+                                            : rho_init[static_cast<size_t>(s) * a.N + cell_at(a, xd, yd, zd)];
+                const double h = wgt<double>(i) * (rho - static_cast<double>(a.rho0[s]));
+                A[pidx(a, s, i, c.z, c.ip)] = ST::enc(static_cast<T>(h), a.scale);
+            }
         }
     }
 }
@@ -1183,29 +1713,23 @@ template <typename ST>
 __global__ void k_canonical(Args<typename ST::T> a, const typename ST::E* __restrict__ A, int s, int i,
                             double* __restrict__ out)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-    const int x = n % a.nx, y = (n / a.nx) % a.ny, z = n / (a.nx * a.ny);
-    const int res = reservoir_of(a, x, y, z);
-    const int cxi = CX[0] * 0;  // silence unused warning patterns
-    (void)cxi;
-    int dx = 0, dy = 0, dz = 0;
-    // runtime direction: small table walk
-    for (int k = 0; k < kQ; ++k)
-        if (k == i) { dx = CX[k]; dy = CY[k]; dz = CZ[k]; }
-    double w = 0;
-    for (int k = 0; k < kQ; ++k)
-        if (k == i) w = wgt<double>(k);
-    double v;
-    if (res >= 0) {
-        v = w * (static_cast<double>(a.res_dr[res][s]) + static_cast<double>(a.rho0[s]));
-    } else {
-        const int xs = (x - dx + a.nx) % a.nx, ys = (y - dy + a.ny) % a.ny, zs = (z - dz + a.nz) % a.nz;
-        const int src = (zs * a.ny + ys) * a.nx + xs;
-        v = static_cast<double>(ST::dec(A[static_cast<size_t>(s * kQ + i) * a.N + src], a.inv_scale)) +
-            w * static_cast<double>(a.rho0[s]);
+    int dx, dy, dz;
+    double w;
+    dir_of(i, dx, dy, dz, w);
+    CELL_LOOP(n, a.N)
+    {
+        const Cell c = cell_of(a, n);
+        const int res = reservoir_of(a, c.x, c.y, c.z);
+        double v;
+        if (res >= 0) {
+            v = w * (static_cast<double>(a.res_dr[res][s]) + static_cast<double>(a.rho0[s]));
+        } else {
+            const int xs = (c.x - dx + a.nx) % a.nx, ys = (c.y - dy + a.ny) % a.ny, zs = (c.z - dz + a.nz) % a.nz;
+            v = static_cast<double>(ST::dec(A[pidx(a, s, i, zs, ys * a.nx + xs)], a.inv_scale)) +
+                w * static_cast<double>(a.rho0[s]);
+        }
+        out[n] = v;
     }
-    out[n] = v;
 }
 
 template <typename ST>
@@ -1213,132 +1737,177 @@ __global__ void k_set_canonical(Args<typename ST::T> a, const double* __restrict
                                 typename ST::E* __restrict__ A)
 {
     using T = typename ST::T;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-    const int x = n % a.nx, y = (n / a.nx) % a.ny, z = n / (a.nx * a.ny);
-    int dx = 0, dy = 0, dz = 0;
-    double w = 0;
-    for (int k = 0; k < kQ; ++k)
-        if (k == i) { dx = CX[k]; dy = CY[k]; dz = CZ[k]; w = wgt<double>(k); }
-    // A_i(y) = f_i(y + c_i)
-    const int xd = (x + dx + a.nx) % a.nx, yd = (y + dy + a.ny) % a.ny, zd = (z + dz + a.nz) % a.nz;
-    const int d = (zd * a.ny + yd) * a.nx + xd;
-    const double h = in[d] - w * static_cast<double>(a.rho0[s]);
-    A[static_cast<size_t>(s * kQ + i) * a.N + n] = ST::enc(static_cast<T>(h), a.scale);
-}
-
-template <typename ST>
-__global__ void k_density(Args<typename ST::T> a, int ncomp, const typename ST::E* __restrict__ A,
-                          double* __restrict__ rho)
-{
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-    const int x = n % a.nx, y = (n / a.nx) % a.ny, z = n / (a.nx * a.ny);
-    const int res = reservoir_of(a, x, y, z);
-    const PullIdx q = pull_idx(x, y, z, a.nx, a.ny, a.nz);
-    for (int s = 0; s < ncomp; ++s) {
-        double acc = 0;
-        if (res >= 0) {
-            acc = static_cast<double>(a.res_dr[res][s]);
-        } else {
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) {
-                const int src = q.pln[CZ[i] + 1] + q.row[CY[i] + 1] + q.col[CX[i] + 1];
-                acc += static_cast<double>(ST::dec(A[static_cast<size_t>(s * kQ + i) * a.N + src], a.inv_scale));
-            }
-        }
-        rho[static_cast<size_t>(s) * a.N + n] = static_cast<double>(a.rho0[s]) + acc;
+    int dx, dy, dz;
+    double w;
+    dir_of(i, dx, dy, dz, w);
+    CELL_LOOP(n, a.N)
+    {
+        const Cell c = cell_of(a, n);
+        // A_i(y) = f_i(y + c_i)
+        const int xd = (c.x + dx + a.nx) % a.nx, yd = (c.y + dy + a.ny) % a.ny, zd = (c.z + dz + a.nz) % a.nz;
+        const double h = in[cell_at(a, xd, yd, zd)] - w * static_cast<double>(a.rho0[s]);
+        A[pidx(a, s, i, c.z, c.ip)] = ST::enc(static_cast<T>(h), a.scale);
     }
 }
 
 constexpr int kRedThreads = 256;
 
-template <typename ST>
-__global__ __launch_bounds__(kRedThreads) void k_moments(Args<typename ST::T> a, int ncomp, int c_ns, double G_s,
-                                                         double Gads0, double Gads1, double gG_p,
-                                                         const typename ST::E* __restrict__ A,
-                                                         const float* __restrict__ ns, const double* __restrict__ rho,
-                                                         double* __restrict__ u_out, double* __restrict__ p_out,
-                                                         double* __restrict__ partials)
+// Sum of v over the block, the same on every run: a butterfly over each
+// wave's 64 lanes (cross-lane moves, no LDS round trips or barriers), then
+// the waves' sums in wave order; thread k < K writes out[k].
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* __restrict__ out)
 {
-    __shared__ double red[5][kRedThreads];
+    __shared__ double ws[kRedThreads / 64][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    const int wv = static_cast<int>(threadIdx.x) >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) ws[wv][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kRedThreads / 64; ++w) s += ws[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Diagnostics, first pass (the only one that reads the populations): per cell
+// the FP64 densities rho_s (Eq. rho_BGK) and first moments j_s (Eq. mom_BGK) of
+// the pre-collision state; writes rho [ncomp][N] and, when m_out is given, the
+// local part of rho u_macro of Eq. (HMCSC_u_macro), sum_s (1 - n_s)(j_s +
+// F_ext,s / 2) with F_ext,s of Eq. (SC_F_ext), into m_out [3][N].  Block
+// totals {M_0, M_1, sum of that local part} go to partials[block][5].
+template <typename ST>
+__global__ __launch_bounds__(kRedThreads) void k_dens(Args<typename ST::T> a, int ncomp, int c_ns,
+                                                      const typename ST::E* __restrict__ A,
+                                                      const float* __restrict__ ns, double* __restrict__ rho,
+                                                      double* __restrict__ m_out, double* __restrict__ partials)
+{
+    double acc[5] = {0, 0, 0, 0, 0};
+    CELL_LOOP(n, a.N)
+    {
+        const Cell c = cell_of(a, n);
+        const int res = reservoir_of(a, c.x, c.y, c.z);
+        const int xs[3] = {wrap_inc(c.x, a.nx), c.x, wrap_dec(c.x, a.nx)};  // x - c, c = -1, 0, 1
+        const int ys[3] = {wrap_inc(c.y, a.ny), c.y, wrap_dec(c.y, a.ny)};
+        const int zs[3] = {wrap_inc(c.z, a.nz), c.z, wrap_dec(c.z, a.nz)};
+        double rs[2] = {0, 0}, j[2][3] = {{0, 0, 0}, {0, 0, 0}}, rtot = 0;
+        for (int s = 0; s < ncomp; ++s) {
+            double d = 0;
+            if (res >= 0) {
+                d = static_cast<double>(a.res_dr[res][s]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    const double h = static_cast<double>(
+                        ST::dec(A[pidx(a, s, i, zs[CZ[i] + 1], ys[CY[i] + 1] * a.nx + xs[CX[i] + 1])], a.inv_scale));
+                    d += h;
+                    j[s][0] += CX[i] * h;
+                    j[s][1] += CY[i] * h;
+                    j[s][2] += CZ[i] * h;
+                }
+            }
+            rs[s] = static_cast<double>(a.rho0[s]) + d;
+            rho[static_cast<size_t>(s) * a.N + n] = rs[s];
+            rtot += rs[s];
+        }
+        double m[3] = {0, 0, 0};
+        for (int s = 0; s < ncomp; ++s) {
+            const double wfl = 1.0 - static_cast<double>(ns[static_cast<size_t>(c_ns == 2 ? s : 0) * a.N + n]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double fext = rtot > 0 ? rs[s] / rtot * static_cast<double>(a.F[d]) : 0.0;
+                m[d] += wfl * (j[s][d] + fext / 2.0);
+            }
+        }
+        if (m_out)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) m_out[static_cast<size_t>(d) * a.N + n] = m[d];
+        acc[0] += rs[0];
+        acc[1] += rs[1];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[2 + d] += m[d];
+    }
+    block_sum<5>(acc, partials + static_cast<size_t>(blockIdx.x) * 5);
+}
+
+// Diagnostics, second pass (densities and n_s only): the half cohesion and
+// adhesion forces of Eqs. (SC_F_inter), (SC_F_ads) weighted by (1 - n_s), the
+// rest of rho u_macro.  When u is given it holds the first pass's local part
+// and receives u_macro of Eq. (HMCSC_u_macro); p receives Eq. (SC_pressure).
+// Block totals {0, 0, sum of the force part} go to partials[block][5].
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_force(Args<T> a, int ncomp, int c_ns, double G_s, double Gads0,
+                                                       double Gads1, double gG_p, const float* __restrict__ ns,
+                                                       const double* __restrict__ rho, double* __restrict__ u,
+                                                       double* __restrict__ p_out, double* __restrict__ partials)
+{
     double acc[5] = {0, 0, 0, 0, 0};
     const double Gads[2] = {Gads0, Gads1};
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < a.N; n += gridDim.x * blockDim.x) {
-        const int x = n % a.nx, y = (n / a.nx) % a.ny, z = n / (a.nx * a.ny);
-        const int res = reservoir_of(a, x, y, z);
-        const PullIdx q = pull_idx(x, y, z, a.nx, a.ny, a.nz);
+    CELL_LOOP(n, a.N)
+    {
+        const Cell c = cell_of(a, n);
         // neighbours x + c_i (note: opposite of the pull)
-        const int xp = wrap_inc(x, a.nx), xm = wrap_dec(x, a.nx);
-        const int yp = wrap_inc(y, a.ny), ym = wrap_dec(y, a.ny);
-        const int zp = wrap_inc(z, a.nz), zm = wrap_dec(z, a.nz);
-        const int cols[3] = {xm, x, xp}, rows[3] = {ym, y, yp}, plns[3] = {zm, z, zp};
-        double rs[2] = {0, 0}, j[2][3] = {{0, 0, 0}, {0, 0, 0}}, rtot = 0;
+        const int cols[3] = {wrap_dec(c.x, a.nx), c.x, wrap_inc(c.x, a.nx)};
+        const int rows[3] = {wrap_dec(c.y, a.ny), c.y, wrap_inc(c.y, a.ny)};
+        const int plns[3] = {wrap_dec(c.z, a.nz), c.z, wrap_inc(c.z, a.nz)};
+        double rs[2] = {0, 0}, rtot = 0;
         for (int s = 0; s < ncomp; ++s) {
             rs[s] = rho[static_cast<size_t>(s) * a.N + n];
             rtot += rs[s];
-            if (res < 0) {
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    const int src = q.pln[CZ[i] + 1] + q.row[CY[i] + 1] + q.col[CX[i] + 1];
-                    const double h = static_cast<double>(ST::dec(A[static_cast<size_t>(s * kQ + i) * a.N + src], a.inv_scale));
-                    j[s][0] += CX[i] * h; j[s][1] += CY[i] * h; j[s][2] += CZ[i] * h;
-                }
-            }
         }
         double m[3] = {0, 0, 0};
         for (int s = 0; s < ncomp; ++s) {
             double gi[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
-            const int cn = c_ns == 2 ? s : 0;
+            const size_t cn = static_cast<size_t>(c_ns == 2 ? s : 0);
 #pragma unroll
             for (int i = 1; i < kQ; ++i) {
-                const int nb = (plns[CZ[i] + 1] * a.ny + rows[CY[i] + 1]) * a.nx + cols[CX[i] + 1];
+                const int64_t nb = cell_at(a, cols[CX[i] + 1], rows[CY[i] + 1], plns[CZ[i] + 1]);
                 const double wi = wgt<double>(i);
                 if (ncomp == 2) {
                     const double r = rho[static_cast<size_t>(1 - s) * a.N + nb];
                     gi[0] += wi * r * CX[i]; gi[1] += wi * r * CY[i]; gi[2] += wi * r * CZ[i];
                 }
-                const double v = static_cast<double>(ns[static_cast<size_t>(cn) * a.N + nb]);
+                const double v = static_cast<double>(ns[cn * a.N + nb]);
                 ga[0] += wi * v * CX[i]; ga[1] += wi * v * CY[i]; ga[2] += wi * v * CZ[i];
             }
-            const double nsx = static_cast<double>(ns[static_cast<size_t>(cn) * a.N + n]);
-            for (int d = 0; d < 3; ++d) {
-                const double fext = rtot > 0 ? rs[s] / rtot * static_cast<double>(a.F[d]) : 0.0;
-                const double ft = -rs[s] * G_s * gi[d] - rs[s] * Gads[s] * ga[d] + fext;
-                m[d] += (1.0 - nsx) * (j[s][d] + ft / 2.0);
-            }
+            const double wfl = 1.0 - static_cast<double>(ns[cn * a.N + n]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) m[d] += wfl * ((-rs[s] * G_s * gi[d] - rs[s] * Gads[s] * ga[d]) / 2.0);
         }
-        double u[3];
-        for (int d = 0; d < 3; ++d) u[d] = rtot > 0 ? m[d] / rtot : 0.0;
-        if (u_out)
-            for (int d = 0; d < 3; ++d) u_out[static_cast<size_t>(d) * a.N + n] = u[d];
+        if (u)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double& ud = u[static_cast<size_t>(d) * a.N + n];
+                ud = rtot > 0 ? (ud + m[d]) / rtot : 0.0;
+            }
         if (p_out) p_out[n] = (rtot + (ncomp == 2 ? gG_p * rs[0] * rs[1] : 0.0)) / 3.0;
-        acc[0] += rs[0];
-        acc[1] += rs[1];
+#pragma unroll
         for (int d = 0; d < 3; ++d) acc[2 + d] += m[d];
     }
-    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 5) partials[blockIdx.x * 5 + threadIdx.x] = red[threadIdx.x][0];
+    block_sum<5>(acc, partials + static_cast<size_t>(blockIdx.x) * 5);
 }
 
 // Electrolyte-filling diagnostics (Sec. 4) from the FP64 fields: per-block
 // sums of p and cell counts over the inlet and outlet slabs (Eq. CapPressure),
 // and of (1 - n_s) [rho_comp >= threshold] and (1 - n_s) over the pore slab
 // (Eq. Saturation).
-__global__ __launch_bounds__(kRedThreads) void k_fill(int nx, int ny, int nz, int N, FillQuery q, int ns_field,
+__global__ __launch_bounds__(kRedThreads) void k_fill(int nx, int ny, int nz, int64_t N, FillQuery q, int ns_field,
                                                       const double* __restrict__ rho, const double* __restrict__ p,
                                                       const float* __restrict__ ns, double* __restrict__ partials)
 {
-    __shared__ double red[6][kRedThreads];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
-        const int x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    CELL_LOOP(n, N)
+    {
+        const int z = static_cast<int>(n / plane);
+        const int ip = static_cast<int>(n - z * plane);
+        const int x = ip % nx, y = ip / nx;
         const int c = q.axis == 0 ? x : (q.axis == 1 ? y : z);
         if (c >= q.inlet_lo && c < q.inlet_hi) {
             acc[0] += p[n];
@@ -1354,14 +1923,8 @@ __global__ __launch_bounds__(kRedThreads) void k_fill(int nx, int ny, int nz, in
             acc[5] += wfl;
         }
     }
-    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 6) partials[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+    (void)nz;
+    block_sum<6>(acc, partials + static_cast<size_t>(blockIdx.x) * 6);
 }
 
 // Fixed-order sum of nblocks partials of K doubles each (one block): the
@@ -1370,26 +1933,23 @@ template <int K>
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partials, int nblocks,
                                                         double* __restrict__ out)
 {
-    __shared__ double red[K][kRedThreads];
     double acc[K];
+#pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += kRedThreads)
-        for (int k = 0; k < K; ++k) acc[k] += partials[b * K + k];
-    for (int k = 0; k < K; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < K) out[threadIdx.x] = red[threadIdx.x][0];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += partials[static_cast<size_t>(b) * K + k];
+    block_sum<K>(acc, out);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers.
 
-bool tile_supported(int tx, int ty)
+bool pair_layout(int storage, int ncomp) { return (storage == kF16 || storage == kBF16) && ncomp == 2; }
+
+bool tile_supported(int storage, int ncomp, int tx, int ty)
 {
+    if (pair_layout(storage, ncomp)) return tx == 64 && (ty == 13 || ty == 4);
     return (tx == 128 && ty == 4) || (tx == 64 && (ty == 4 || ty == 8)) || (tx == 32 && (ty == 4 || ty == 8 || ty == 16));
 }
 
@@ -1417,9 +1977,23 @@ static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const voi
     a.nzc = (p.nz + l.zchunk - 1) / l.zchunk;
     a.t = static_cast<uint32_t>(t);
     const int nblocks = a.ntx * a.nty * a.nzc;
-    hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE>), dim3(nblocks), dim3(NC * TX * TY), 0, st, a,
-                       static_cast<const E*>(A), static_cast<E*>(B), ns);
+    hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE>), dim3(nblocks), dim3(kThreads<ST, NC, TX, TY>), 0, st,
+                       a, static_cast<const E*>(A), static_cast<E*>(B), ns);
     return hipGetLastError();
+}
+
+// The default tiles of a layout, with the one-plane and GS-WBS instances.
+template <typename ST, int NC, int CNS, int TX, int TY>
+static hipError_t step_default(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
+                               hipStream_t st)
+{
+    constexpr int SC = kForcingShanChen, GUO = kForcingGuo;
+    const bool one = p.nz == 1;
+    if (p.forcing == kForcingGuo)
+        return one ? step_t<ST, NC, CNS, TX, TY, GUO, true>(p, l, t, A, B, ns, st)
+                   : step_t<ST, NC, CNS, TX, TY, GUO, false>(p, l, t, A, B, ns, st);
+    return one ? step_t<ST, NC, CNS, TX, TY, SC, true>(p, l, t, A, B, ns, st)
+               : step_t<ST, NC, CNS, TX, TY, SC, false>(p, l, t, A, B, ns, st);
 }
 
 // Tile shapes (TX x TY cells per block) compiled in.
@@ -1427,29 +2001,21 @@ template <typename ST, int NC, int CNS>
 static hipError_t step_ty(const Problem& p, const Launch& l, int64_t t, const void* A, void* B, const float* ns,
                           hipStream_t st)
 {
-    constexpr int SC = kForcingShanChen, GUO = kForcingGuo;
-    // one-cell-deep domains on the default tiles: the one-plane instances
-    const bool one = p.nz == 1;
-    if (p.forcing == kForcingGuo) {  // the GS-WBS: the default tiles only
-        if (l.tile_x == 64 && l.tile_y == 8)
-            return one ? step_t<ST, NC, CNS, 64, 8, GUO, true>(p, l, t, A, B, ns, st)
-                       : step_t<ST, NC, CNS, 64, 8, GUO, false>(p, l, t, A, B, ns, st);
-        if (l.tile_x == 64 && l.tile_y == 4)
-            return one ? step_t<ST, NC, CNS, 64, 4, GUO, true>(p, l, t, A, B, ns, st)
-                       : step_t<ST, NC, CNS, 64, 4, GUO, false>(p, l, t, A, B, ns, st);
+    constexpr int SC = kForcingShanChen;
+    if constexpr (kPair<ST, NC>) {
+        if (l.tile_x == 64 && l.tile_y == 13) return step_default<ST, NC, CNS, 64, 13>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 64 && l.tile_y == 4) return step_default<ST, NC, CNS, 64, 4>(p, l, t, A, B, ns, st);
+        return hipErrorInvalidValue;
+    } else {
+        if (l.tile_x == 64 && l.tile_y == 8) return step_default<ST, NC, CNS, 64, 8>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 64 && l.tile_y == 4) return step_default<ST, NC, CNS, 64, 4>(p, l, t, A, B, ns, st);
+        if (p.forcing == kForcingGuo || p.nz == 1) return hipErrorInvalidValue;  // default tiles only
+        if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4, SC, false>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4, SC, false>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8, SC, false>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16, SC, false>(p, l, t, A, B, ns, st);
         return hipErrorInvalidValue;
     }
-    if (l.tile_x == 64 && l.tile_y == 8)
-        return one ? step_t<ST, NC, CNS, 64, 8, SC, true>(p, l, t, A, B, ns, st)
-                   : step_t<ST, NC, CNS, 64, 8, SC, false>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 64 && l.tile_y == 4)
-        return one ? step_t<ST, NC, CNS, 64, 4, SC, true>(p, l, t, A, B, ns, st)
-                   : step_t<ST, NC, CNS, 64, 4, SC, false>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 128 && l.tile_y == 4) return step_t<ST, NC, CNS, 128, 4, SC, false>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 4) return step_t<ST, NC, CNS, 32, 4, SC, false>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 8) return step_t<ST, NC, CNS, 32, 8, SC, false>(p, l, t, A, B, ns, st);
-    if (l.tile_x == 32 && l.tile_y == 16) return step_t<ST, NC, CNS, 32, 16, SC, false>(p, l, t, A, B, ns, st);
-    return hipErrorInvalidValue;
 }
 
 template <typename ST>
@@ -1473,7 +2039,11 @@ hipError_t launch_step(const Problem& p, const Launch& l, int64_t t, const void*
     }
 }
 
-static unsigned cell_blocks(int64_t N) { return static_cast<unsigned>((N + 255) / 256); }
+// Grid of a cell loop: enough blocks to fill the device a few times over.
+static unsigned cell_blocks(int64_t N)
+{
+    return static_cast<unsigned>(std::min<int64_t>((N + 255) / 256, int64_t(1) << 20));
+}
 
 template <typename F>
 static hipError_t by_storage(int storage, F&& f)
@@ -1520,47 +2090,40 @@ hipError_t launch_set_canonical(const Problem& p, const double* in, int s, int i
     });
 }
 
-hipError_t launch_density(const Problem& p, const void* A, double* rho, hipStream_t st)
-{
-    return by_storage(p.storage, [&](auto tag) {
-        using ST = decltype(tag);
-        Args<typename ST::T> a = make_args<typename ST::T>(p);
-        hipLaunchKernelGGL((k_density<ST>), dim3(cell_blocks(p.N)), dim3(256), 0, st, a, p.ncomp,
-                           static_cast<const typename ST::E*>(A), rho);
-        return hipGetLastError();
-    });
-}
-
 int moments_max_blocks() { return 1024; }
 
-hipError_t launch_moments(const Problem& p, const void* A, const float* ns, const double* rho, double* u,
-                          double* pr, double* partials, int* nblocks, hipStream_t st)
+static int diag_blocks(int64_t N)
 {
-    const int nb = static_cast<int>(std::min<int64_t>(moments_max_blocks(), (p.N + kRedThreads - 1) / kRedThreads));
-    *nblocks = nb;
-    return by_storage(p.storage, [&](auto tag) {
-        using ST = decltype(tag);
-        Args<typename ST::T> a = make_args<typename ST::T>(p);
-        hipLaunchKernelGGL((k_moments<ST>), dim3(nb), dim3(kRedThreads), 0, st, a, p.ncomp, p.c_ns, p.G_s,
-                           p.Gads_s[0], p.Gads_s[1], p.g_scale * p.G_inter, static_cast<const typename ST::E*>(A),
-                           ns, rho, u, pr, partials);
-        return hipGetLastError();
-    });
+    return static_cast<int>(std::min<int64_t>(moments_max_blocks(), (N + kRedThreads - 1) / kRedThreads));
 }
 
-hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st)
+hipError_t launch_diagnostics(const Problem& p, const void* A, const float* ns, bool forces, double* rho, double* u,
+                              double* pr, double* partials, double* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce<5>, dim3(1), dim3(kRedThreads), 0, st, partials, nblocks, out);
+    const int nb = diag_blocks(p.N);
+    hipError_t e = by_storage(p.storage, [&](auto tag) {
+        using ST = decltype(tag);
+        Args<typename ST::T> a = make_args<typename ST::T>(p);
+        hipLaunchKernelGGL((k_dens<ST>), dim3(nb), dim3(kRedThreads), 0, st, a, p.ncomp, p.c_ns,
+                           static_cast<const typename ST::E*>(A), ns, rho, u, partials);
+        if (forces)
+            hipLaunchKernelGGL((k_force<typename ST::T>), dim3(nb), dim3(kRedThreads), 0, st, a, p.ncomp, p.c_ns, p.G_s,
+                               p.Gads_s[0], p.Gads_s[1], p.g_scale * p.G_inter, ns, rho, u, pr,
+                               partials + static_cast<size_t>(nb) * 5);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce<5>, dim3(1), dim3(kRedThreads), 0, st, partials, forces ? 2 * nb : nb, out);
     return hipGetLastError();
 }
 
 hipError_t launch_fill(const Problem& p, const FillQuery& q, const double* rho, const double* pr, const float* ns,
                        double* partials, double* out, hipStream_t st)
 {
-    const int nb = static_cast<int>(std::min<int64_t>(moments_max_blocks(), (p.N + kRedThreads - 1) / kRedThreads));
+    const int nb = diag_blocks(p.N);
     const int ns_field = p.c_ns == 2 ? q.comp : 0;
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kRedThreads), 0, st, p.nx, p.ny, p.nz, static_cast<int>(p.N), q,
-                       ns_field, rho, pr, ns, partials);
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kRedThreads), 0, st, p.nx, p.ny, p.nz, p.N, q, ns_field, rho, pr, ns,
+                       partials);
     hipLaunchKernelGGL(k_reduce<6>, dim3(1), dim3(kRedThreads), 0, st, partials, nb, out);
     return hipGetLastError();
 }
@@ -1617,76 +2180,73 @@ int batch_encode(int storage, const BatchDomain* d, int n, int tile_x, int tile_
 template <typename ST, int NC, int CNS, int TX, int TY>
 static hipError_t batch_t(const void* table, int k, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_step_batch<ST, NC, CNS, TX, TY>), dim3(grid), dim3(NC * TX * TY), 0, st,
+    hipLaunchKernelGGL((k_step_batch<ST, NC, CNS, TX, TY>), dim3(grid), dim3(kThreads<ST, NC, TX, TY>), 0, st,
                        static_cast<const char*>(table), k);
     return hipGetLastError();
 }
-
-template <typename ST, int NC, int CNS>
-static hipError_t batch_tile(int tx, int ty, const void* table, int k, int grid, hipStream_t st)
-{
-    if (tx == 64 && ty == 8) return batch_t<ST, NC, CNS, 64, 8>(table, k, grid, st);
-    if (tx == 32 && ty == 8) return batch_t<ST, NC, CNS, 32, 8>(table, k, grid, st);
-    return hipErrorInvalidValue;
-}
-
-template <typename ST>
-static hipError_t batch_st(int ncomp, int c_ns, int tx, int ty, const void* table, int k, int grid, hipStream_t st)
-{
-    if (ncomp == 1) return batch_tile<ST, 1, 1>(tx, ty, table, k, grid, st);
-    if (c_ns == 1) return batch_tile<ST, 2, 1>(tx, ty, table, k, grid, st);
-    return batch_tile<ST, 2, 2>(tx, ty, table, k, grid, st);
-}
-
-bool batch_tile_supported(int tx, int ty) { return (tx == 64 && ty == 8) || (tx == 32 && ty == 8); }
 
 template <typename ST, int NC, int CNS, int TX, int TY>
 static int batch_occ_t()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<ST, NC, CNS, TX, TY>, NC * TX * TY, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<ST, NC, CNS, TX, TY>, kThreads<ST, NC, TX, TY>,
+                                                     0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 
-template <typename ST, int NC, int CNS>
-static int batch_occ_tile(int tx, int ty)
+// One function for every (format, components, n_s fields, tile) of the
+// batched kernel: f receives the compiled instance's launcher and occupancy.
+template <typename ST, int NC, int CNS, typename F>
+static hipError_t batch_tile(int tx, int ty, F&& f)
 {
-    if (tx == 64 && ty == 8) return batch_occ_t<ST, NC, CNS, 64, 8>();
-    if (tx == 32 && ty == 8) return batch_occ_t<ST, NC, CNS, 32, 8>();
-    return 1;
+    if constexpr (kPair<ST, NC>) {
+        if (tx == 64 && ty == 13) return f(batch_t<ST, NC, CNS, 64, 13>, batch_occ_t<ST, NC, CNS, 64, 13>);
+    } else {
+        if (tx == 64 && ty == 8) return f(batch_t<ST, NC, CNS, 64, 8>, batch_occ_t<ST, NC, CNS, 64, 8>);
+        if (tx == 32 && ty == 8) return f(batch_t<ST, NC, CNS, 32, 8>, batch_occ_t<ST, NC, CNS, 32, 8>);
+    }
+    return hipErrorInvalidValue;
 }
 
-template <typename ST>
-static int batch_occ_st(int ncomp, int c_ns, int tx, int ty)
+template <typename F>
+static hipError_t batch_dispatch(int storage, int ncomp, int c_ns, int tx, int ty, F&& f)
 {
-    if (ncomp == 1) return batch_occ_tile<ST, 1, 1>(tx, ty);
-    if (c_ns == 1) return batch_occ_tile<ST, 2, 1>(tx, ty);
-    return batch_occ_tile<ST, 2, 2>(tx, ty);
+    return by_storage(storage, [&](auto tag) {
+        using ST = decltype(tag);
+        if (ncomp == 1) return batch_tile<ST, 1, 1>(tx, ty, f);
+        if (c_ns == 1) return batch_tile<ST, 2, 1>(tx, ty, f);
+        return batch_tile<ST, 2, 2>(tx, ty, f);
+    });
+}
+
+bool batch_tile_supported(int storage, int ncomp, int tx, int ty)
+{
+    if (pair_layout(storage, ncomp)) return tx == 64 && ty == 13;
+    return (tx == 64 && ty == 8) || (tx == 32 && ty == 8);
+}
+
+void batch_default_tile(int storage, int ncomp, int* tx, int* ty)
+{
+    *tx = 64;
+    *ty = pair_layout(storage, ncomp) ? 13 : 8;
 }
 
 int batch_blocks_per_cu(int storage, int ncomp, int c_ns, int tile_x, int tile_y)
 {
-    switch (storage) {
-    case kF64: return batch_occ_st<F64>(ncomp, c_ns, tile_x, tile_y);
-    case kF32: return batch_occ_st<F32>(ncomp, c_ns, tile_x, tile_y);
-    case kF16: return batch_occ_st<F16>(ncomp, c_ns, tile_x, tile_y);
-    case kBF16: return batch_occ_st<BF16>(ncomp, c_ns, tile_x, tile_y);
-    default: return 1;
-    }
+    int n = 1;
+    (void)batch_dispatch(storage, ncomp, c_ns, tile_x, tile_y, [&](auto, auto occ) {
+        n = occ();
+        return hipSuccess;
+    });
+    return n;
 }
 
 hipError_t launch_step_batch(int storage, int ncomp, int c_ns, int tile_x, int tile_y, const void* table, int k,
                              int grid, hipStream_t st)
 {
-    switch (storage) {
-    case kF64: return batch_st<F64>(ncomp, c_ns, tile_x, tile_y, table, k, grid, st);
-    case kF32: return batch_st<F32>(ncomp, c_ns, tile_x, tile_y, table, k, grid, st);
-    case kF16: return batch_st<F16>(ncomp, c_ns, tile_x, tile_y, table, k, grid, st);
-    case kBF16: return batch_st<BF16>(ncomp, c_ns, tile_x, tile_y, table, k, grid, st);
-    default: return hipErrorInvalidValue;
-    }
+    return batch_dispatch(storage, ncomp, c_ns, tile_x, tile_y,
+                          [&](auto launch, auto) { return launch(table, k, grid, st); });
 }
 
 }  // namespace hm

@@ -21,8 +21,11 @@ int validate(const lbm_domain* d, const lbm_params* p)
 {
     if (!d || !p) return LBM_EINVAL;
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return LBM_EINVAL;
-    const int64_t N = static_cast<int64_t>(d->nx) * d->ny * d->nz;
-    if (N >= (int64_t(1) << 31)) return LBM_EINVAL;
+    // each plane block of 19 direction arrays is addressed through one
+    // buffer descriptor with 32-bit offsets
+    const int64_t plane = static_cast<int64_t>(d->nx) * d->ny;
+    if (plane * hm::kQ * 8 >= (int64_t(1) << 32)) return LBM_EINVAL;
+    if (static_cast<int64_t>(d->nz) * plane >= (int64_t(1) << 40)) return LBM_EINVAL;
     if (p->ncomp < 1 || p->ncomp > 2) return LBM_EINVAL;
     if (p->c_ns < 1 || p->c_ns > 2 || p->c_ns > p->ncomp) return LBM_EINVAL;
     for (int s = 0; s < p->ncomp; ++s) {
@@ -33,9 +36,6 @@ int validate(const lbm_domain* d, const lbm_params* p)
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->F_ext[a])) return LBM_EINVAL;
     if (p->storage < LBM_F64 || p->storage > LBM_BF16S) return LBM_EINVAL;
-    // the step kernel addresses the 19 direction arrays of one component through
-    // one 32-bit buffer range
-    if (static_cast<uint64_t>(N) * hm::kQ * hm::storage_bytes(p->storage) >= (uint64_t(1) << 32)) return LBM_EINVAL;
     if (p->store_scale_log2 < -30 || p->store_scale_log2 > 30) return LBM_EINVAL;
     if ((p->storage == LBM_F64 || p->storage == LBM_F32) && p->store_scale_log2 != 0) return LBM_EINVAL;
     if (p->n_res < 0 || p->n_res > LBM_MAX_RES) return LBM_EINVAL;
@@ -95,15 +95,19 @@ hm::Launch choose_launch(const hm::Problem& p, int cus)
 {
     hm::Launch l{};
     // FP64 with two components needs the smaller tile to stay within the
-    // register file (no spills)
+    // register file (no spills); the pair kernel runs one thread per cell
+    // plus three ring waves, so its 1024-thread tile is 64 x 13
     const bool wide = p.storage == hm::kF64 && p.ncomp == 2;
+    const bool pair = hm::pair_layout(p.storage, p.ncomp);
+    const int dflt_y = pair ? (p.ny >= 13 ? 13 : 4) : ((p.ny >= 8 && !wide) ? 8 : 4);
     l.tile_x = env_int("LBM_TILE_X", 64);
-    l.tile_y = env_int("LBM_TILE_Y", (p.ny >= 8 && !wide) ? 8 : 4);
-    // the GS-WBS is compiled for the default tiles only
-    if (!hm::tile_supported(l.tile_x, l.tile_y) ||
-        (p.forcing == hm::kForcingGuo && !(l.tile_x == 64 && (l.tile_y == 8 || l.tile_y == 4)))) {
+    l.tile_y = env_int("LBM_TILE_Y", dflt_y);
+    // the GS-WBS and one-plane domains use the default tile widths only
+    if (!hm::tile_supported(p.storage, p.ncomp, l.tile_x, l.tile_y) ||
+        ((p.forcing == hm::kForcingGuo || p.nz == 1) &&
+         !(l.tile_x == 64 && (pair ? (l.tile_y == 13 || l.tile_y == 4) : (l.tile_y == 8 || l.tile_y == 4))))) {
         l.tile_x = 64;
-        l.tile_y = wide ? 4 : 8;
+        l.tile_y = dflt_y;
     }
     const int ntx = (p.nx + l.tile_x - 1) / l.tile_x;
     const int nty = (p.ny + l.tile_y - 1) / l.tile_y;
@@ -144,18 +148,15 @@ using namespace hm_rt;
         if ((expr) != hipSuccess) return LBM_EDEVICE;  \
     } while (0)
 
-int hm_rt::compute_totals(lbm_ctx* c, bool fields, lbm_totals* tot)
+int hm_rt::compute_totals(lbm_ctx* c, bool fields, bool forces, lbm_totals* tot)
 {
     double* rho = reinterpret_cast<double*>(c->scratch + c->sl.rho);
     double* u = reinterpret_cast<double*>(c->scratch + c->sl.u);
     double* p = reinterpret_cast<double*>(c->scratch + c->sl.p);
     double* part = reinterpret_cast<double*>(c->scratch + c->sl.partials);
     double* tots = reinterpret_cast<double*>(c->scratch + c->sl.totals);
-    int nb = 0;
-    HIP_TRY(hm::launch_density(c->prob, c->buf[c->cur], rho, c->stream));
-    HIP_TRY(hm::launch_moments(c->prob, c->buf[c->cur], c->ns, rho, fields ? u : nullptr, fields ? p : nullptr,
-                               part, &nb, c->stream));
-    HIP_TRY(hm::launch_reduce(part, nb, tots, c->stream));
+    HIP_TRY(hm::launch_diagnostics(c->prob, c->buf[c->cur], c->ns, forces || fields, rho, fields ? u : nullptr,
+                                   fields ? p : nullptr, part, tots, c->stream));
     double h[5];
     HIP_TRY(hipMemcpyAsync(h, tots, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -306,7 +307,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps)
         c->t += 1;
         if (c->prm.check_every > 0 && c->t % c->prm.check_every == 0) {
             lbm_totals tt;
-            const int rc = compute_totals(c, false, &tt);
+            const int rc = compute_totals(c, false, false, &tt);
             if (rc) return rc;
             if (!tt.finite) return LBM_EUNSTABLE;
         }
@@ -329,7 +330,7 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, lbm_totals* tot)
 {
     if (!c) return LBM_EINVAL;
     const bool fields = rho || u || p;
-    const int rc = compute_totals(c, fields, tot);
+    const int rc = compute_totals(c, fields, true, tot);
     if (rc) return rc;
     const int64_t N = c->prob.N;
     if (rho)
@@ -342,7 +343,7 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, lbm_totals* tot)
 int lbm_totals_get(lbm_ctx* c, lbm_totals* tot)
 {
     if (!c || !tot) return LBM_EINVAL;
-    return compute_totals(c, false, tot);
+    return compute_totals(c, false, true, tot);
 }
 
 int lbm_get_populations(lbm_ctx* c, double* f)
@@ -398,7 +399,7 @@ int lbm_fill_state_get(lbm_ctx* c, const lbm_fill_query* q, lbm_fill_state* out)
     if (!slab_ok(q->inlet_lo, q->inlet_hi, true) || !slab_ok(q->outlet_lo, q->outlet_hi, true) ||
         !slab_ok(q->pore_lo, q->pore_hi, false) || !std::isfinite(q->threshold))
         return LBM_EINVAL;
-    const int rc = compute_totals(c, true, nullptr);  // FP64 densities and pressure into the scratch
+    const int rc = compute_totals(c, true, true, nullptr);  // FP64 densities and pressure into the scratch
     if (rc) return rc;
     hm::FillQuery f{q->axis, q->inlet_lo, q->inlet_hi, q->outlet_lo, q->outlet_hi, q->pore_lo, q->pore_hi, q->comp,
                     q->threshold};

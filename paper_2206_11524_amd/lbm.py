@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(PKG, "libhmcsc.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ENOTFOUND, LBM_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+STORE_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 MAX_RES = 4
 Q = 19
 
@@ -387,7 +388,7 @@ class Server:
     """Continuous-batching server (worker thread inside the library)."""
 
     def __init__(self, storage="f16s", ncomp=2, c_ns=1, max_slots=64, steps_per_tick=100, max_cells=192 ** 3,
-                 hbm_budget_bytes=0, tile=(64, 8), policy="fair", run_cells=0):
+                 hbm_budget_bytes=0, tile=(0, 0), policy="fair", run_cells=0):
         self.lib = _serve_lib()
         cfg = ServerCfg(int(hbm_budget_bytes), int(max_slots), int(steps_per_tick),
                         STORAGE[storage] if isinstance(storage, str) else int(storage), ncomp, c_ns,

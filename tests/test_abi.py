@@ -135,12 +135,29 @@ def test_binding_structs_match_the_header_layout(tmp_path):
             assert got[(st, fname)] == getattr(cls, fname).offset, (st, fname)
 
 
-@pytest.mark.parametrize("shape", [(0, 4, 4), (4, -1, 4), (2048, 2048, 1024)])
+@pytest.mark.parametrize("shape", [(0, 4, 4), (4, -1, 4), (8192, 4096, 1), (65536, 256, 65536)])
 def test_bad_domains_rejected(lib, shape):
+    """Empty axes, a plane too large for one 32-bit addressed plane block
+    (19 * 8 bytes per cell), and 2^40 cells or more are rejected."""
     p = lbm.make_params()
     d = lbm.Domain(*shape)
     s = lbm.Sizes()
     assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("storage", ["f16s", "f32", "f64"])
+def test_domains_beyond_4_gib_per_component_are_accepted(lib, storage):
+    """Each plane block has its own buffer descriptor, so one component's 19
+    direction arrays may span more than 4 GiB: 1024^3 cells (8.6e9 cells per
+    buffer in FP16 with two components) and 2^31 cells and more are sized
+    (whether they fit is decided by the device allocation at creation)."""
+    for shape in [(1024, 1024, 1024), (2048, 1024, 1024)]:
+        p = lbm.make_params(storage=storage)
+        d = lbm.Domain(*shape)
+        s = lbm.Sizes()
+        assert lib.lbm_required_bytes(C.byref(d), C.byref(p), C.byref(s)) == lbm.LBM_OK
+        N = shape[0] * shape[1] * shape[2]
+        assert s.pop_bytes >= 2 * 19 * N * lbm.STORE_BYTES[storage] > 1 << 32
 
 
 def test_bounce_back_fraction_outside_unit_interval_rejected(lib):

@@ -245,18 +245,34 @@ def test_launch_configuration_does_not_change_results(monkeypatch):
 
 @pytest.mark.parametrize("storage", ["f16s", "bf16s"])
 @pytest.mark.parametrize("shape", [(98, 30, 37), (130, 9, 11), (24, 17, 13)])
-def test_tile_width_does_not_change_16bit_results(monkeypatch, storage, shape):
-    """With 16-bit storage too, 64- and 32-cell tile rows (different ring,
+def test_tile_shape_does_not_change_16bit_results(monkeypatch, storage, shape):
+    """Two components in a 16-bit format (the pair kernel): 64 x 13 and 64 x 4
+    tiles and z-chunks of 3 planes and of the whole domain (different ring,
     halo and block decomposition) give identical bits, also for ragged tiles,
-    rows shorter than a tile and a reservoir slab across x."""
+    rows shorter than a tile and a reservoir slab across x.  One component in
+    the same format (the split kernel) with 64- and 32-cell rows likewise."""
     w = inputs.random_state(shape, 31, ns_choices=[0.0, 0.4, 1.0], rho_range=(0.3, 0.7))
     w.G, w.G_ads, w.F_ext = 0.7, (0.2, -0.2), (1e-4, 2e-4, -1e-4)
     w.reservoirs = [(0, 0, 2, (0.6, 0.35))]
     outs = []
+    for ty, zc in ((13, 0), (4, 0), (13, 3), (4, shape[2])):
+        monkeypatch.setenv("LBM_TILE_Y", str(ty))
+        monkeypatch.setenv("LBM_ZCHUNK", str(zc))
+        sim = lbm.from_workload(w, storage=storage)
+        sim.step(9)
+        outs.append(sim.populations())
+        sim.close()
+    assert np.isfinite(outs[0]).all()
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+    monkeypatch.delenv("LBM_ZCHUNK")
+    w1 = inputs.random_state(shape, 32, ncomp=1, ns_choices=[0.0, 0.4, 1.0], rho_range=(0.3, 0.7))
+    w1.F_ext = (1e-4, 2e-4, -1e-4)
+    outs = []
     for tx in (64, 32):
         monkeypatch.setenv("LBM_TILE_X", str(tx))
         monkeypatch.setenv("LBM_TILE_Y", "8")
-        sim = lbm.from_workload(w, storage=storage)
+        sim = lbm.from_workload(w1, storage=storage)
         sim.step(9)
         outs.append(sim.populations())
         sim.close()
