@@ -47,6 +47,9 @@ struct Launch {
 // other runs use the split layout [s][z][i][y][x].
 bool pair_layout(int storage, int ncomp);
 
+// Rows of the default tile of the pair kernel (64 cells wide).
+int pair_tile_y();
+
 // True if the tile shape is compiled in for this format and component count.
 bool tile_supported(int storage, int ncomp, int tile_x, int tile_y);
 

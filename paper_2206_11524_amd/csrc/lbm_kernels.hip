@@ -181,31 +181,39 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t x)
 }
 
 // Two 16-bit values of one (cell, direction) in one 32-bit word of the pair
-// layout: component 0 in the low half, component 1 in the high half.  Each
-// half is decoded and rounded exactly as a lone 16-bit value would be.
+// layout: component 0 in the low half, component 1 in the high half.  The
+// pair kernel works on the stored scale (h * 2^k): the power-of-two factor
+// is folded into the few per-cell coefficients instead of every value, which
+// changes no bit (scaling by 2^k commutes with rounding).
 template <typename ST>
 struct PairCodec {
-    static __device__ __forceinline__ float lo(uint32_t v, float inv_scale)
-    {
-        return ST::dec(static_cast<uint16_t>(v & 0xffffu), inv_scale);
-    }
-    static __device__ __forceinline__ float hi(uint32_t v, float inv_scale)
-    {
-        return ST::dec(static_cast<uint16_t>(v >> 16), inv_scale);
-    }
-    static __device__ __forceinline__ uint32_t enc(float a, float b, float scale)
+    static __device__ __forceinline__ float lo(uint32_t v) { return ST::dec(static_cast<uint16_t>(v & 0xffffu), 1.0f); }
+    static __device__ __forceinline__ float hi(uint32_t v) { return ST::dec(static_cast<uint16_t>(v >> 16), 1.0f); }
+    static __device__ __forceinline__ uint32_t enc(float a, float b)
     {
         if constexpr (std::is_same_v<ST, BF16>) {
-            const bf162_t h = {static_cast<__bf16>(a * scale), static_cast<__bf16>(b * scale)};
+            const bf162_t h = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
             return __builtin_bit_cast(uint32_t, h);
         } else {
-            const half2_t h = {static_cast<_Float16>(a * scale), static_cast<_Float16>(b * scale)};
+            const half2_t h = {static_cast<_Float16>(a), static_cast<_Float16>(b)};
             return __builtin_bit_cast(uint32_t, h);
         }
     }
-    static __device__ __forceinline__ uint32_t enc_sr(float a, float b, float scale, uint32_t ra, uint32_t rb)
+    // stochastic rounding (see F16::enc_sr) of a into the low and b into the
+    // high half of one word
+    static __device__ __forceinline__ uint32_t enc_sr(float a, float b, uint32_t ra, uint32_t rb)
     {
-        return static_cast<uint32_t>(ST::enc_sr(a, scale, ra)) | (static_cast<uint32_t>(ST::enc_sr(b, scale, rb)) << 16);
+        if constexpr (std::is_same_v<ST, BF16>) {
+            bf162_t h = {0, 0};
+            h = __builtin_amdgcn_cvt_sr_bf16_f32(h, a, ra << 16, false);
+            h = __builtin_amdgcn_cvt_sr_bf16_f32(h, b, rb << 16, true);
+            return __builtin_bit_cast(uint32_t, h);
+        } else {
+            half2_t h = {0, 0};
+            h = __builtin_amdgcn_cvt_sr_f16_f32(h, a, ra << 16, false);
+            h = __builtin_amdgcn_cvt_sr_f16_f32(h, b, rb << 16, true);
+            return __builtin_bit_cast(uint32_t, h);
+        }
     }
 };
 
@@ -324,6 +332,47 @@ __device__ __forceinline__ bool reservoir_dr2(const Args<T>& a, int x, int y, in
         }
     }
     return in;
+}
+
+// Reservoir membership as bit masks (pair kernel): bit r is set when the cell
+// lies in slot r.  Slots along x or y depend on the cell's column only, so a
+// thread computes their bits once; slots along z depend on the plane only, the
+// same for the whole block.  The lowest set bit is the slot that applies
+// (slots are searched in order, as in reservoir_dr).
+template <typename T>
+__device__ __forceinline__ uint32_t reservoir_xy_bits(const Args<T>& a, int x, int y)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < kMaxRes; ++r) {
+        const int c = a.res_axis[r] == 0 ? x : y;
+        if (r < a.n_res && a.res_axis[r] != 2 && c >= a.res_lo[r] && c < a.res_hi[r]) m |= 1u << r;
+    }
+    return m;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t reservoir_z_bits(const Args<T>& a, int z)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < kMaxRes; ++r)
+        if (r < a.n_res && a.res_axis[r] == 2 && z >= a.res_lo[r] && z < a.res_hi[r]) m |= 1u << r;
+    return m;
+}
+
+// shifted densities of the slot of the lowest bit of m (m != 0)
+template <typename T>
+__device__ __forceinline__ void reservoir_pick(const Args<T>& a, uint32_t m, T& dr0, T& dr1)
+{
+    dr0 = a.res_dr[kMaxRes - 1][0];
+    dr1 = a.res_dr[kMaxRes - 1][1];
+#pragma unroll
+    for (int r = kMaxRes - 2; r >= 0; --r) {
+        const bool hit = (m >> r) & 1u;
+        dr0 = hit ? a.res_dr[r][0] : dr0;
+        dr1 = hit ? a.res_dr[r][1] : dr1;
+    }
 }
 
 __device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
@@ -636,14 +685,20 @@ __device__ __forceinline__ void cell_velocity_pair(const Args<float>& a, int me,
     }
     const T inv_den = den > T(0) ? recip(den) : T(0);
     const T inv_rho = rho > T(0) ? recip(rho) : T(0);
+    // one stencil at a time (a scheduling fence after each): all 54 or 72
+    // neighbour reads in flight at once would need as many registers
     T ga[CNS][3];
 #pragma unroll
-    for (int cn = 0; cn < CNS; ++cn) stencil<T, float, LW>(ns_m + cn * LP, ns_0 + cn * LP, ns_p + cn * LP, me, ga[cn]);
+    for (int cn = 0; cn < CNS; ++cn) {
+        stencil<T, float, LW>(ns_m + cn * LP, ns_0 + cn * LP, ns_p + cn * LP, me, ga[cn]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int cn = CNS == 2 ? s : 0;
         T gi[3];
         stencil<T, T, LW>(rho_m + (1 - s) * LP, rho_0 + (1 - s) * LP, rho_p + (1 - s) * LP, me, gi);
+        __builtin_amdgcn_sched_barrier(0);
         const bool present = rho_own[s] > T(0);
         const T tau_s = a.tau[s], Gads = a.Gads_s[s];
 #pragma unroll
@@ -1206,8 +1261,9 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
 // so the cell waves keep their registers for the prefetch.
 //
 // LDS: four density / n_s plane slots (plane p in slot p mod 4, one barrier
-// per plane) and the raw words of the plane staged last, private to each cell
-// thread.
+// per plane) and the raw words of the last two planes staged, private to each
+// cell thread: the collision reads its plane's words from LDS, so no register
+// holds them while the next plane's loads are in flight.
 template <int CNS, int TX, int TY>
 struct PairShared {
     static constexpr int LW = TX + 2;
@@ -1215,17 +1271,30 @@ struct PairShared {
     static constexpr int NT = TX * TY;
     float rho[4][2][LP];
     float ns[4][CNS][LP];
-    uint32_t hs[kQ][NT];
+    uint32_t hs[2][kQ][NT];
 };
 
 constexpr int kPairRing = 192;  // ring / n_s threads per block (three waves)
+#ifndef LBM_PAIR_TY
+#define LBM_PAIR_TY 9
+#endif
+constexpr int kPairTY = LBM_PAIR_TY;  // rows of the default pair tile (64 x kPairTY cells)
 
 // Planes a cell wave keeps in flight ahead of the one it stages (1 or 2).
 #ifndef LBM_PAIR_AHEAD
-#define LBM_PAIR_AHEAD 1
+#define LBM_PAIR_AHEAD 2
 #endif
 
-template <typename ST, int CNS, int TX, int TY, int FS, bool ONE = false>
+// Rounding of the stored words: kRoundNearest and kRoundStochastic fix it at
+// compile time; kRoundEither follows the domain's flag without a branch
+// (both roundings computed and one selected), so that the stores of a
+// collision form one straight sequence (after a branch between two store
+// sequences the compiler's wait counts lose track of how many stores were
+// issued, and its waits for the next plane's loads then wait for the
+// stores as well).
+constexpr int kRoundNearest = 0, kRoundStochastic = 1, kRoundEither = 2;
+
+template <typename ST, int CNS, int TX, int TY, int FS, bool ONE, int RND>
 __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint32_t* __restrict__ A,
                                                uint32_t* __restrict__ B, const float* __restrict__ ns, int L,
                                                uint32_t t, PairShared<CNS, TX, TY>& sh)
@@ -1267,27 +1336,54 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
             e[i] = __builtin_amdgcn_raw_buffer_load_b32(r3[CZ[i] + 1], q.o[CY[i] + 1][CX[i] + 1],
                                                         static_cast<uint32_t>(i) * dir_bytes, 0);
     };
-    // densities rho_0, rho_1 of a cell from its raw words, with the Dirichlet
-    // density of a reservoir cell (a select per value, skipped as a whole when
-    // no lane of the wave is in a reservoir)
-    auto densities = [&](int cx, int cy, int cz, const uint32_t e[kQ], T& r0, T& r1) {
-        T h0[kQ], h1[kQ];
+    // densities rho_0, rho_1 of a cell from its raw words, and with MOM its
+    // first moments (Eq. mom_BGK) too; a reservoir cell has the Dirichlet
+    // density instead, summed in the same order over the rest populations
+    // w_i dr (computed only when a lane of the wave is in a reservoir), and
+    // first moments 0 (w_i = w_ibar).  The words are decoded into the running
+    // sums, never held as 38 floats.
+    auto moments = [&](uint32_t rbits, const uint32_t e[kQ], T& r0, T& r1, T* j) {
+        T s0 = PC::lo(e[0]), s1 = PC::hi(e[0]);
+        T j0[3] = {T(0), T(0), T(0)}, j1[3] = {T(0), T(0), T(0)};
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            h0[i] = PC::lo(e[i], a.inv_scale);
-            h1[i] = PC::hi(e[i], a.inv_scale);
-        }
-        T dr0, dr1;
-        const bool in = reservoir_dr2(a, cx, cy, cz, dr0, dr1);
-        if (__builtin_amdgcn_ballot_w64(in) != 0) {
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) {
-                h0[i] = in ? wgt<T>(i) * dr0 : h0[i];
-                h1[i] = in ? wgt<T>(i) * dr1 : h1[i];
+        for (int i = 1; i <= 9; ++i) {
+            const T a0 = PC::lo(e[i]), b0 = PC::lo(e[i + 9]), a1 = PC::hi(e[i]), b1 = PC::hi(e[i + 9]);
+            s0 += a0 + b0;
+            s1 += a1 + b1;
+            if (j) {
+                if (CX[i]) { j0[0] += CX[i] > 0 ? a0 - b0 : b0 - a0; j1[0] += CX[i] > 0 ? a1 - b1 : b1 - a1; }
+                if (CY[i]) { j0[1] += CY[i] > 0 ? a0 - b0 : b0 - a0; j1[1] += CY[i] > 0 ? a1 - b1 : b1 - a1; }
+                if (CZ[i]) { j0[2] += CZ[i] > 0 ? a0 - b0 : b0 - a0; j1[2] += CZ[i] > 0 ? a1 - b1 : b1 - a1; }
             }
         }
-        r0 = a.rho0[0] + sum19(h0);
-        r1 = a.rho0[1] + sum19(h1);
+        s0 *= a.inv_scale;
+        s1 *= a.inv_scale;
+        if (j) {
+            const bool in = rbits != 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                j[d] = in ? T(0) : j0[d] * a.inv_scale;
+                j[3 + d] = in ? T(0) : j1[d] * a.inv_scale;
+            }
+        }
+        const bool in = rbits != 0;
+        if (__builtin_amdgcn_ballot_w64(in) != 0) {
+            T dr0, dr1;
+            reservoir_pick(a, rbits, dr0, dr1);
+            T w0 = wgt<T>(0) * dr0, w1 = wgt<T>(0) * dr1;
+#pragma unroll
+            for (int i = 1; i <= 9; ++i) {
+                w0 += wgt<T>(i) * dr0 + wgt<T>(i + 9) * dr0;
+                w1 += wgt<T>(i) * dr1 + wgt<T>(i + 9) * dr1;
+            }
+            s0 = in ? w0 : s0;
+            s1 = in ? w1 : s1;
+        }
+        r0 = a.rho0[0] + s0;
+        r1 = a.rho0[1] + s1;
+    };
+    auto densities = [&](uint32_t rbits, const uint32_t e[kQ], T& r0, T& r1) {
+        moments(rbits, e, r0, r1, static_cast<T*>(nullptr));
     };
     auto rslot = [&](int p) { return (p - zs + 1) & 3; };
 
@@ -1308,6 +1404,7 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         const int ry = ((y0 + rly) % a.ny + a.ny) % a.ny;
         const int rme = (rly + 1) * LW + (rlx + 1);
         const PlaneOffs qring = plane_offs<4>(rx, ry, a.nx, a.ny);
+        const uint32_t rxy = reservoir_xy_bits(a, rx, ry);
         // n_s cells of this thread (LDS index, in-plane index); past the list
         // a thread repeats its first cell, the corner (x0 - 1, y0 - 1)
         const int nsw = TXe + 2, nsh = TYe + 2;
@@ -1340,7 +1437,7 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         // consume the loads of plane p into LDS slot `slot`
         auto consume_ring = [&](int p, int slot) {
             T r0, r1;
-            densities(rx, ry, p, er, r0, r1);
+            densities(rxy | reservoir_z_bits(a, p), er, r0, r1);
             if (ring) {
                 s_rho[slot][0][rme] = r0;
                 s_rho[slot][1][rme] = r1;
@@ -1386,33 +1483,30 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
     const PlaneOffs qme = plane_offs<4>(x, y, a.nx, a.ny);
     const uint32_t own = static_cast<uint32_t>(y * a.nx + x) * 4u;
     const uint32_t t_key = fmix32(t ^ kGolden);  // stochastic rounding: time part of the counter
+    const uint32_t cxy = reservoir_xy_bits(a, x, y);
 
     // Collision of plane z from the raw words hz of the own cell and the LDS
     // slots of planes z-1, z, z+1.  The words are decoded where they are used
     // (twice: first moments, then the relaxation) rather than held as 38
     // floats.
-    auto collide = [&](int z, int sm, int s0, int sp, const uint32_t hz[kQ]) {
+    auto collide = [&](int z, int sm, int s0, int sp, const T (&jm)[6], auto&& wd) {
+        const uint32_t rbits = cxy | reservoir_z_bits(a, z);
+        const bool in = rbits != 0;
         T dr0, dr1;
-        const bool in = reservoir_dr2(a, x, y, z, dr0, dr1);
-        uint32_t w[kQ];
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) w[i] = hz[i];
-        auto h0 = [&](int i) { return in ? wgt<T>(i) * dr0 : PC::lo(w[i], a.inv_scale); };
-        auto h1 = [&](int i) { return in ? wgt<T>(i) * dr1 : PC::hi(w[i], a.inv_scale); };
-        T jc[2][3];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            T j3[3] = {T(0), T(0), T(0)};
-#pragma unroll
-            for (int i = 1; i <= 9; ++i) {
-                const T hi_ = c == 0 ? h0(i) : h1(i), ho_ = c == 0 ? h0(i + 9) : h1(i + 9);
-                if (CX[i]) j3[0] += CX[i] > 0 ? hi_ - ho_ : ho_ - hi_;
-                if (CY[i]) j3[1] += CY[i] > 0 ? hi_ - ho_ : ho_ - hi_;
-                if (CZ[i]) j3[2] += CZ[i] > 0 ? hi_ - ho_ : ho_ - hi_;
-            }
-#pragma unroll
-            for (int d = 0; d < 3; ++d) jc[c][d] = j3[d];
-        }
+        reservoir_pick(a, rbits, dr0, dr1);
+        // populations on the stored scale: h_i * 2^k
+        const T ds0 = dr0 * a.scale, ds1 = dr1 * a.scale;
+        // (the word is read unconditionally: a conditional operator around
+        // the read would become a branch per value)
+        auto h0 = [&](int i) {
+            const T v = PC::lo(wd(i));
+            return in ? wgt<T>(i) * ds0 : v;
+        };
+        auto h1 = [&](int i) {
+            const T v = PC::hi(wd(i));
+            return in ? wgt<T>(i) * ds1 : v;
+        };
+        const T jc[2][3] = {{jm[0], jm[1], jm[2]}, {jm[3], jm[4], jm[5]}};
         T ueq[2][3], rho_own[2], n[2], fo[2][3];
         if constexpr (FS == kForcingGuo) {
             T um[3];
@@ -1427,17 +1521,19 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
             cell_velocity_pair<CNS, LW, LP>(a, me, &s_rho[sm][0][0], &s_rho[s0][0][0], &s_rho[sp][0][0],
                                             &s_ns[sm][0][0], &s_ns[s0][0][0], &s_ns[sp][0][0], jc, ueq, rho_own, n);
         }
-        // an empty asm that claims to change the words: the decodes below are
-        // then not merged with those of the first moments (which would keep
-        // all 38 decoded values live across the velocity computation)
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) asm volatile("" : "+v"(w[i]));
-        const RelaxCoef<T> k0 = relax_coef<T>(a, 0, rho_own[0], ueq[0], n[0]);
-        const RelaxCoef<T> k1 = relax_coef<T>(a, 1, rho_own[1], ueq[1], n[1]);
+        RelaxCoef<T> k0 = relax_coef<T>(a, 0, rho_own[0], ueq[0], n[0]);
+        RelaxCoef<T> k1 = relax_coef<T>(a, 1, rho_own[1], ueq[1], n[1]);
         GuoCoef<T> g0{}, g1{};
         if constexpr (FS == kForcingGuo) {
             g0 = guo_coef<T>(a, 0, n[0], fo[0], ueq[0]);
             g1 = guo_coef<T>(a, 1, n[1], fo[1], ueq[1]);
+        }
+        // the terms not proportional to h go to the stored scale
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            k0.K0[c] *= a.scale; k0.K1[c] *= a.scale; k0.K2[c] *= a.scale;
+            k1.K0[c] *= a.scale; k1.K1[c] *= a.scale; k1.K2[c] *= a.scale;
+            g0.gw[c] *= a.scale; g1.gw[c] *= a.scale;
         }
         auto rest = [&](const RelaxCoef<T>& k, const GuoCoef<T>& g, T h) {
             if constexpr (FS == kForcingGuo) return relax_rest_guo(k, g, h);
@@ -1448,39 +1544,35 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
             else relax_dir(k, i, hi_, ho_, pi, po);
         };
         const rsrc_t rz = blk(B, z);
-        if (a.sr) {
-            // the random streams of the split kernels: per (cell, component)
-            // fmix32 of the counter, then one xorshift32 step per direction pair
+        // the random streams of the split kernels: per (cell, component)
+        // fmix32 of the counter, then one xorshift32 step per direction pair
+        uint32_t r0 = 0, r1 = 0;
+        if constexpr (RND != kRoundNearest) {
             const uint32_t cell = static_cast<uint32_t>(z) * static_cast<uint32_t>(plane) + static_cast<uint32_t>(y * a.nx + x);
-            uint32_t r0 = fmix32(t_key ^ (2u * cell)) | 1u;
-            uint32_t r1 = fmix32(t_key ^ (2u * cell + 1u)) | 1u;
-            __builtin_amdgcn_raw_buffer_store_b32(
-                PC::enc_sr(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), a.scale, r0 >> 16, r1 >> 16), rz, own, 0u, kNT);
+            r0 = fmix32(t_key ^ (2u * cell)) | 1u;
+            r1 = fmix32(t_key ^ (2u * cell + 1u)) | 1u;
+        }
+        const uint32_t sr_mask = RND == kRoundEither ? 0u - static_cast<uint32_t>(a.sr != 0) : 0u;
+        auto word = [&](T v0, T v1, uint32_t ra, uint32_t rb) -> uint32_t {
+            if constexpr (RND == kRoundStochastic) return PC::enc_sr(v0, v1, ra, rb);
+            else if constexpr (RND == kRoundNearest) return PC::enc(v0, v1);
+            else return (PC::enc_sr(v0, v1, ra, rb) & sr_mask) | (PC::enc(v0, v1) & ~sr_mask);
+        };
+        __builtin_amdgcn_raw_buffer_store_b32(word(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), r0 >> 16, r1 >> 16), rz, own,
+                                              0u, kNT);
 #pragma unroll
-            for (int i = 1; i <= 9; ++i) {
-                T pi0, po0, pi1, po1;
-                pairdir(k0, g0, i, h0(i), h0(i + 9), pi0, po0);
-                pairdir(k1, g1, i, h1(i), h1(i + 9), pi1, po1);
+        for (int i = 1; i <= 9; ++i) {
+            T pi0, po0, pi1, po1;
+            pairdir(k0, g0, i, h0(i), h0(i + 9), pi0, po0);
+            pairdir(k1, g1, i, h1(i), h1(i + 9), pi1, po1);
+            if constexpr (RND != kRoundNearest) {
                 r0 = xorshift32(r0);
                 r1 = xorshift32(r1);
-                __builtin_amdgcn_raw_buffer_store_b32(PC::enc_sr(pi0, pi1, a.scale, r0 & 0xffffu, r1 & 0xffffu), rz,
-                                                      own, static_cast<uint32_t>(i) * dir_bytes, kNT);
-                __builtin_amdgcn_raw_buffer_store_b32(PC::enc_sr(po0, po1, a.scale, r0 >> 16, r1 >> 16), rz, own,
-                                                      static_cast<uint32_t>(i + 9) * dir_bytes, kNT);
             }
-        } else {
-            __builtin_amdgcn_raw_buffer_store_b32(PC::enc(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), a.scale), rz, own,
-                                                  0u, kNT);
-#pragma unroll
-            for (int i = 1; i <= 9; ++i) {
-                T pi0, po0, pi1, po1;
-                pairdir(k0, g0, i, h0(i), h0(i + 9), pi0, po0);
-                pairdir(k1, g1, i, h1(i), h1(i + 9), pi1, po1);
-                __builtin_amdgcn_raw_buffer_store_b32(PC::enc(pi0, pi1, a.scale), rz, own,
-                                                      static_cast<uint32_t>(i) * dir_bytes, kNT);
-                __builtin_amdgcn_raw_buffer_store_b32(PC::enc(po0, po1, a.scale), rz, own,
-                                                      static_cast<uint32_t>(i + 9) * dir_bytes, kNT);
-            }
+            __builtin_amdgcn_raw_buffer_store_b32(word(pi0, pi1, r0 & 0xffffu, r1 & 0xffffu), rz, own,
+                                                  static_cast<uint32_t>(i) * dir_bytes, kNT);
+            __builtin_amdgcn_raw_buffer_store_b32(word(po0, po1, r0 >> 16, r1 >> 16), rz, own,
+                                                  static_cast<uint32_t>(i + 9) * dir_bytes, kNT);
         }
     };
 
@@ -1490,60 +1582,64 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         const int slot = rslot(0);
         uint32_t r1[kQ];
         issue(0, qme, r1);
-        T d0, d1;
-        densities(x, y, 0, r1, d0, d1);
+        T d0, d1, jm[6];
+        moments(cxy | reservoir_z_bits(a, 0), r1, d0, d1, jm);
         s_rho[slot][0][me] = d0;
         s_rho[slot][1][me] = d1;
         __syncthreads();
-        collide(0, slot, slot, slot, r1);
+        collide(0, slot, slot, slot, jm, [&](int i) { return r1[i]; });
         return;
     } else {
-        // Three planes at a time, as in the split kernel: plane z is collided
-        // from registers, plane z+1 waits in LDS (hs), and the loads of plane
+        // Three planes at a time: the words of planes z and z+1 wait in LDS
+        // (hs, double-buffered), plane z is collided, and the loads of plane
         // z+1+AHEAD are in flight over the barrier and the collision.  No
         // memory access in the sweep is conditional (a skipped access would
         // make the compiler's waits drain the loads kept in flight).
         constexpr int AHEAD = LBM_PAIR_AHEAD;
         constexpr bool DEEP = AHEAD == 2;
-        uint32_t* hsp = &sh.hs[0][0] + tl;
+        auto hbuf = [&](int p) { return &sh.hs[(p - zs + 2) & 1][0][0] + tl; };
         uint32_t rA[kQ];
         uint32_t rB[DEEP ? kQ : 1];
-        // Stage plane p, whose loads are in rc: its densities go to LDS and its
-        // words to hs, whose previous content (the plane before) moves to hz;
-        // then the loads of plane pn are issued into rc.
-        auto stage_pipe = [&](int p, int slot, int pn, uint32_t hz[kQ], uint32_t rc[kQ]) {
+        // Stage plane p, whose loads are in rc: its densities go to LDS and
+        // its words to hs; then the loads of plane pn are issued into rc.
+        // the first moments of a staged plane wait in registers for its
+        // collision (two sets, for the planes z and z+1)
+        T jA[6], jB[6];
+        auto stage_pipe = [&](int p, int pu, int pn, uint32_t rc[kQ], T (&jm)[6]) {
             T d0, d1;
-            densities(x, y, p, rc, d0, d1);
+            moments(cxy | reservoir_z_bits(a, p), rc, d0, d1, jm);
+            const int slot = rslot(pu);
             s_rho[slot][0][me] = d0;
             s_rho[slot][1][me] = d1;
+            uint32_t* hw = hbuf(pu);
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) {
-                hz[i] = hsp[i * NT];
-                hsp[i * NT] = rc[i];
-            }
+            for (int i = 0; i < kQ; ++i) hw[i * NT] = rc[i];
             __builtin_amdgcn_sched_barrier(0);
             issue(pn, qme, rc);
+        };
+        auto collide_z = [&](int z, const T (&jm)[6]) {
+            const uint32_t* hr = hbuf(z);
+            collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jm, [&](int i) { return hr[i * NT]; });
         };
         // the plane whose loads a stage of plane p issues: p + AHEAD, or after
         // the last plane one already staged again (cache hits)
         auto ahead = [&](int p) { return wrapz(p + AHEAD <= ze ? p + AHEAD : ze); };
         uint32_t (&r_odd)[kQ] = rA;
         uint32_t (&r_even)[kQ] = *reinterpret_cast<uint32_t(*)[kQ]>(DEEP ? static_cast<uint32_t*>(rB) : static_cast<uint32_t*>(rA));
-        uint32_t hz[kQ];
-        // prologue: planes zs-1 (densities only) and zs (to hs)
+        // prologue: planes zs-1 (densities only) and zs
         issue(wrapz(zs - 1), qme, r_odd);
         if constexpr (DEEP) issue(zs, qme, r_even);
-        stage_pipe(wrapz(zs - 1), rslot(zs - 1), ahead(zs - 1), hz, r_odd);
-        stage_pipe(zs, rslot(zs), ahead(zs), hz, r_even);
+        stage_pipe(wrapz(zs - 1), zs - 1, ahead(zs - 1), r_odd, jB);
+        stage_pipe(zs, zs, ahead(zs), r_even, jA);
         // unrolled by two so the register sets keep fixed names
         for (int z = zs; z < ze; z += 2) {
-            stage_pipe(wrapz(z + 1), rslot(z + 1), ahead(z + 1), hz, r_odd);
+            stage_pipe(wrapz(z + 1), z + 1, ahead(z + 1), r_odd, jB);
             __syncthreads();
-            collide(z, rslot(z - 1), rslot(z), rslot(z + 1), hz);
+            collide_z(z, jA);
             if (z + 1 >= ze) break;
-            stage_pipe(wrapz(z + 2), rslot(z + 2), ahead(z + 2), hz, r_even);
+            stage_pipe(wrapz(z + 2), z + 2, ahead(z + 2), r_even, jA);
             __syncthreads();
-            collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), hz);
+            collide_z(z + 1, jB);
         }
     }
 }
@@ -1555,7 +1651,7 @@ constexpr bool kPair = sizeof(typename ST::E) == 2 && NC == 2;
 template <typename ST, int NC, int TX, int TY>
 constexpr int kThreads = kPair<ST, NC> ? TX * TY + kPairRing : NC * TX * TY;
 
-template <typename ST, int NC, int CNS, int TX, int TY, int FS, bool ONE>
+template <typename ST, int NC, int CNS, int TX, int TY, int FS, bool ONE, int RND>
 __global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step(Args<typename ST::T> a,
                                                                     const typename ST::E* __restrict__ A,
                                                                     typename ST::E* __restrict__ B,
@@ -1568,8 +1664,8 @@ __global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step(Args<typena
     if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
     if constexpr (kPair<ST, NC>) {
         __shared__ PairShared<CNS, TX, TY> sh;
-        step_tile_pair<ST, CNS, TX, TY, FS, ONE>(a, reinterpret_cast<const uint32_t*>(A), reinterpret_cast<uint32_t*>(B),
-                                                 ns, L, a.t, sh);
+        step_tile_pair<ST, CNS, TX, TY, FS, ONE, RND>(a, reinterpret_cast<const uint32_t*>(A),
+                                                      reinterpret_cast<uint32_t*>(B), ns, L, a.t, sh);
     } else {
         __shared__ TileShared<ST, NC, CNS, TX, TY> sh;
         step_tile<ST, NC, CNS, TX, TY, FS, ONE>(a, A, B, ns, L, a.t, sh);
@@ -1629,11 +1725,18 @@ __global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step_batch(const
         if (k >= e.steps) continue;
         const int cur = (e.parity + k) & 1;
         __syncthreads();  // the previous tile's LDS is no longer read
-        if constexpr (kPair<ST, NC>)
-            step_tile_pair<ST, CNS, TX, TY, kForcingShanChen>(e.a, static_cast<const uint32_t*>(e.buf[cur]),
-                                                              static_cast<uint32_t*>(const_cast<void*>(e.buf[1 - cur])),
-                                                              e.ns, w - e.tile_begin, e.a.t + static_cast<uint32_t>(k), sh);
-        else
+        if constexpr (kPair<ST, NC>) {
+            // the rounding of each domain picks a tile sweep compiled for it
+            const uint32_t* src = static_cast<const uint32_t*>(e.buf[cur]);
+            uint32_t* dst = static_cast<uint32_t*>(const_cast<void*>(e.buf[1 - cur]));
+            const uint32_t tk = e.a.t + static_cast<uint32_t>(k);
+            if (e.a.sr)
+                step_tile_pair<ST, CNS, TX, TY, kForcingShanChen, false, kRoundStochastic>(e.a, src, dst, e.ns,
+                                                                                         w - e.tile_begin, tk, sh);
+            else
+                step_tile_pair<ST, CNS, TX, TY, kForcingShanChen, false, kRoundNearest>(e.a, src, dst, e.ns,
+                                                                                      w - e.tile_begin, tk, sh);
+        } else
             step_tile<ST, NC, CNS, TX, TY, kForcingShanChen>(e.a, static_cast<const E*>(e.buf[cur]),
                                                              static_cast<E*>(const_cast<void*>(e.buf[1 - cur])), e.ns,
                                                              w - e.tile_begin, e.a.t + static_cast<uint32_t>(k), sh);
@@ -1947,9 +2050,11 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
 
 bool pair_layout(int storage, int ncomp) { return (storage == kF16 || storage == kBF16) && ncomp == 2; }
 
+int pair_tile_y() { return kPairTY; }
+
 bool tile_supported(int storage, int ncomp, int tx, int ty)
 {
-    if (pair_layout(storage, ncomp)) return tx == 64 && (ty == 13 || ty == 4);
+    if (pair_layout(storage, ncomp)) return tx == 64 && (ty == kPairTY || ty == 4);
     return (tx == 128 && ty == 4) || (tx == 64 && (ty == 4 || ty == 8)) || (tx == 32 && (ty == 4 || ty == 8 || ty == 16));
 }
 
@@ -1977,8 +2082,19 @@ static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const voi
     a.nzc = (p.nz + l.zchunk - 1) / l.zchunk;
     a.t = static_cast<uint32_t>(t);
     const int nblocks = a.ntx * a.nty * a.nzc;
-    hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE>), dim3(nblocks), dim3(kThreads<ST, NC, TX, TY>), 0, st,
-                       a, static_cast<const E*>(A), static_cast<E*>(B), ns);
+    // the pair kernel is compiled per rounding mode; the split kernels
+    // branch on it (their two store sequences are alike)
+    if constexpr (kPair<ST, NC>) {
+        if (p.stochastic)
+            hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, kRoundStochastic>), dim3(nblocks),
+                               dim3(kThreads<ST, NC, TX, TY>), 0, st, a, static_cast<const E*>(A), static_cast<E*>(B), ns);
+        else
+            hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, kRoundNearest>), dim3(nblocks),
+                               dim3(kThreads<ST, NC, TX, TY>), 0, st, a, static_cast<const E*>(A), static_cast<E*>(B), ns);
+    } else {
+        hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, kRoundEither>), dim3(nblocks),
+                           dim3(kThreads<ST, NC, TX, TY>), 0, st, a, static_cast<const E*>(A), static_cast<E*>(B), ns);
+    }
     return hipGetLastError();
 }
 
@@ -2003,7 +2119,7 @@ static hipError_t step_ty(const Problem& p, const Launch& l, int64_t t, const vo
 {
     constexpr int SC = kForcingShanChen;
     if constexpr (kPair<ST, NC>) {
-        if (l.tile_x == 64 && l.tile_y == 13) return step_default<ST, NC, CNS, 64, 13>(p, l, t, A, B, ns, st);
+        if (l.tile_x == 64 && l.tile_y == kPairTY) return step_default<ST, NC, CNS, 64, kPairTY>(p, l, t, A, B, ns, st);
         if (l.tile_x == 64 && l.tile_y == 4) return step_default<ST, NC, CNS, 64, 4>(p, l, t, A, B, ns, st);
         return hipErrorInvalidValue;
     } else {
@@ -2201,7 +2317,7 @@ template <typename ST, int NC, int CNS, typename F>
 static hipError_t batch_tile(int tx, int ty, F&& f)
 {
     if constexpr (kPair<ST, NC>) {
-        if (tx == 64 && ty == 13) return f(batch_t<ST, NC, CNS, 64, 13>, batch_occ_t<ST, NC, CNS, 64, 13>);
+        if (tx == 64 && ty == kPairTY) return f(batch_t<ST, NC, CNS, 64, kPairTY>, batch_occ_t<ST, NC, CNS, 64, kPairTY>);
     } else {
         if (tx == 64 && ty == 8) return f(batch_t<ST, NC, CNS, 64, 8>, batch_occ_t<ST, NC, CNS, 64, 8>);
         if (tx == 32 && ty == 8) return f(batch_t<ST, NC, CNS, 32, 8>, batch_occ_t<ST, NC, CNS, 32, 8>);
@@ -2222,14 +2338,14 @@ static hipError_t batch_dispatch(int storage, int ncomp, int c_ns, int tx, int t
 
 bool batch_tile_supported(int storage, int ncomp, int tx, int ty)
 {
-    if (pair_layout(storage, ncomp)) return tx == 64 && ty == 13;
+    if (pair_layout(storage, ncomp)) return tx == 64 && ty == kPairTY;
     return (tx == 64 && ty == 8) || (tx == 32 && ty == 8);
 }
 
 void batch_default_tile(int storage, int ncomp, int* tx, int* ty)
 {
     *tx = 64;
-    *ty = pair_layout(storage, ncomp) ? 13 : 8;
+    *ty = pair_layout(storage, ncomp) ? kPairTY : 8;
 }
 
 int batch_blocks_per_cu(int storage, int ncomp, int c_ns, int tile_x, int tile_y)

@@ -96,16 +96,17 @@ hm::Launch choose_launch(const hm::Problem& p, int cus)
     hm::Launch l{};
     // FP64 with two components needs the smaller tile to stay within the
     // register file (no spills); the pair kernel runs one thread per cell
-    // plus three ring waves, so its 1024-thread tile is 64 x 13
+    // plus three ring waves on 64-wide tiles of pair_tile_y() rows
     const bool wide = p.storage == hm::kF64 && p.ncomp == 2;
     const bool pair = hm::pair_layout(p.storage, p.ncomp);
-    const int dflt_y = pair ? (p.ny >= 13 ? 13 : 4) : ((p.ny >= 8 && !wide) ? 8 : 4);
+    const int pty = hm::pair_tile_y();
+    const int dflt_y = pair ? (p.ny >= pty ? pty : 4) : ((p.ny >= 8 && !wide) ? 8 : 4);
     l.tile_x = env_int("LBM_TILE_X", 64);
     l.tile_y = env_int("LBM_TILE_Y", dflt_y);
     // the GS-WBS and one-plane domains use the default tile widths only
     if (!hm::tile_supported(p.storage, p.ncomp, l.tile_x, l.tile_y) ||
         ((p.forcing == hm::kForcingGuo || p.nz == 1) &&
-         !(l.tile_x == 64 && (pair ? (l.tile_y == 13 || l.tile_y == 4) : (l.tile_y == 8 || l.tile_y == 4))))) {
+         !(l.tile_x == 64 && (pair ? (l.tile_y == pty || l.tile_y == 4) : (l.tile_y == 8 || l.tile_y == 4))))) {
         l.tile_x = 64;
         l.tile_y = dflt_y;
     }
