@@ -174,6 +174,20 @@ int lbm_moments(lbm_ctx* ctx, double* rho, double* u, double* p, lbm_totals* tot
 /* FP64 totals only (no per-cell copy-back).  Synchronises. */
 int lbm_totals_get(lbm_ctx* ctx, lbm_totals* tot);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * totals of lbm_totals_get, computed in one pass that keeps no per-cell field
+ * (each cell recomputes its neighbours' densities), with the per-block partial
+ * sums in a fixed 82 KB device array of the library (2048 blocks x 5 doubles
+ * plus the totals), one per device, held until the process ends.  It
+ * allocates nothing and does not touch the context's scratch buffer; any
+ * domain the context accepts fits (the grid strides over the cells with at
+ * most 2048 blocks).  The totals equal lbm_totals_get's up to the order of the
+ * FP64 sums.  Calls that overlap on one device share its array and race:
+ * serialise them.  Synchronises the context stream; LBM_EINVAL for NULL
+ * arguments, LBM_EDEVICE if the array cannot be located or a launch fails. */
+int lbm_totals_get_static(lbm_ctx* ctx, lbm_totals* tot);
+
 /* Electrolyte-filling diagnostics of Sec. 4, on slabs lo <= coordinate[axis]
  * < hi of the current (pre-collision) state at time t:
  *   capillary pressure, Eq. (CapPressure): dp = <p>_inlet - <p>_outlet, the

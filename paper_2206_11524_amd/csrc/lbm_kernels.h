@@ -84,6 +84,12 @@ hipError_t launch_diagnostics(const Problem& p, const void* A, const float* ns, 
 
 int moments_max_blocks();
 
+// The totals of launch_diagnostics (forces included) in one pass that keeps
+// no per-cell field: partial sums of at most max_blocks blocks (5 doubles
+// each) in partials, the totals in out[5].
+hipError_t launch_totals_one_pass(const Problem& p, const void* A, const float* ns, double* partials, int max_blocks,
+                                  double* out, hipStream_t st);
+
 // Slabs of the filling diagnostics (Sec. 4), coordinates along axis.
 struct FillQuery {
     int axis;

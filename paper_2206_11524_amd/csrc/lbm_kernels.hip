@@ -1996,6 +1996,95 @@ __global__ __launch_bounds__(kRedThreads) void k_force(Args<T> a, int ncomp, int
     block_sum<5>(acc, partials + static_cast<size_t>(blockIdx.x) * 5);
 }
 
+// FP64 density of component s at cell (x, y, z) of the pre-collision state:
+// the pulled populations summed in direction order, or the reservoir's
+// prescribed density.
+template <typename ST>
+__device__ __forceinline__ double density_at(const Args<typename ST::T>& a, const typename ST::E* __restrict__ A,
+                                             int s, int x, int y, int z)
+{
+    const int res = reservoir_of(a, x, y, z);
+    double d = 0;
+    if (res >= 0) {
+        d = static_cast<double>(a.res_dr[res][s]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const int xs = (x - CX[i] + a.nx) % a.nx, ys = (y - CY[i] + a.ny) % a.ny, zs = (z - CZ[i] + a.nz) % a.nz;
+            d += static_cast<double>(ST::dec(A[pidx(a, s, i, zs, ys * a.nx + xs)], a.inv_scale));
+        }
+    }
+    return static_cast<double>(a.rho0[s]) + d;
+}
+
+// The FP64 totals of k_dens and k_force in one pass with no per-cell field:
+// each cell recomputes the densities of its 18 neighbours from their pulled
+// populations (19 times the reads of one pass, cache hits for the most part).
+// Block totals {M_0, M_1, J_x, J_y, J_z} go to partials[block][5].
+template <typename ST>
+__global__ __launch_bounds__(kRedThreads) void k_totals_one_pass(Args<typename ST::T> a, int ncomp, int c_ns,
+                                                                 double G_s, double Gads0, double Gads1,
+                                                                 const typename ST::E* __restrict__ A,
+                                                                 const float* __restrict__ ns,
+                                                                 double* __restrict__ partials)
+{
+    double acc[5] = {0, 0, 0, 0, 0};
+    const double Gads[2] = {Gads0, Gads1};
+    CELL_LOOP(n, a.N)
+    {
+        const Cell c = cell_of(a, n);
+        const int res = reservoir_of(a, c.x, c.y, c.z);
+        const int xs[3] = {wrap_inc(c.x, a.nx), c.x, wrap_dec(c.x, a.nx)};  // x - c, c = -1, 0, 1
+        const int ys[3] = {wrap_inc(c.y, a.ny), c.y, wrap_dec(c.y, a.ny)};
+        const int zs[3] = {wrap_inc(c.z, a.nz), c.z, wrap_dec(c.z, a.nz)};
+        double rs[2] = {0, 0}, j[2][3] = {{0, 0, 0}, {0, 0, 0}}, rtot = 0;
+        for (int s = 0; s < ncomp; ++s) {
+            if (res < 0) {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    const double h = static_cast<double>(
+                        ST::dec(A[pidx(a, s, i, zs[CZ[i] + 1], ys[CY[i] + 1] * a.nx + xs[CX[i] + 1])], a.inv_scale));
+                    j[s][0] += CX[i] * h;
+                    j[s][1] += CY[i] * h;
+                    j[s][2] += CZ[i] * h;
+                }
+            }
+            rs[s] = density_at<ST>(a, A, s, c.x, c.y, c.z);
+            rtot += rs[s];
+        }
+        double m[3] = {0, 0, 0};
+        for (int s = 0; s < ncomp; ++s) {
+            double gi[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
+            const size_t cn = static_cast<size_t>(c_ns == 2 ? s : 0);
+#pragma unroll
+            for (int i = 1; i < kQ; ++i) {
+                // neighbour x + c_i
+                const int nx_ = (c.x + CX[i] + a.nx) % a.nx, ny_ = (c.y + CY[i] + a.ny) % a.ny,
+                          nz_ = (c.z + CZ[i] + a.nz) % a.nz;
+                const double wi = wgt<double>(i);
+                if (ncomp == 2) {
+                    const double r = density_at<ST>(a, A, 1 - s, nx_, ny_, nz_);
+                    gi[0] += wi * r * CX[i]; gi[1] += wi * r * CY[i]; gi[2] += wi * r * CZ[i];
+                }
+                const double v = static_cast<double>(ns[cn * a.N + cell_at(a, nx_, ny_, nz_)]);
+                ga[0] += wi * v * CX[i]; ga[1] += wi * v * CY[i]; ga[2] += wi * v * CZ[i];
+            }
+            const double wfl = 1.0 - static_cast<double>(ns[cn * a.N + n]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double fext = rtot > 0 ? rs[s] / rtot * static_cast<double>(a.F[d]) : 0.0;
+                const double ft = -rs[s] * G_s * gi[d] - rs[s] * Gads[s] * ga[d] + fext;
+                m[d] += wfl * (j[s][d] + ft / 2.0);
+            }
+        }
+        acc[0] += rs[0];
+        acc[1] += rs[1];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[2 + d] += m[d];
+    }
+    block_sum<5>(acc, partials + static_cast<size_t>(blockIdx.x) * 5);
+}
+
 // Electrolyte-filling diagnostics (Sec. 4) from the FP64 fields: per-block
 // sums of p and cell counts over the inlet and outlet slabs (Eq. CapPressure),
 // and of (1 - n_s) [rho_comp >= threshold] and (1 - n_s) over the pore slab
@@ -2230,6 +2319,22 @@ hipError_t launch_diagnostics(const Problem& p, const void* A, const float* ns, 
     });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce<5>, dim3(1), dim3(kRedThreads), 0, st, partials, forces ? 2 * nb : nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_totals_one_pass(const Problem& p, const void* A, const float* ns, double* partials, int max_blocks,
+                                  double* out, hipStream_t st)
+{
+    const int nb = static_cast<int>(std::min<int64_t>(max_blocks, (p.N + kRedThreads - 1) / kRedThreads));
+    hipError_t e = by_storage(p.storage, [&](auto tag) {
+        using ST = decltype(tag);
+        Args<typename ST::T> a = make_args<typename ST::T>(p);
+        hipLaunchKernelGGL((k_totals_one_pass<ST>), dim3(nb), dim3(kRedThreads), 0, st, a, p.ncomp, p.c_ns, p.G_s,
+                           p.Gads_s[0], p.Gads_s[1], static_cast<const typename ST::E*>(A), ns, partials);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce<5>, dim3(1), dim3(kRedThreads), 0, st, partials, nb, out);
     return hipGetLastError();
 }
 

@@ -80,6 +80,7 @@ SIGNATURES = {
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Totals)]),
     "lbm_totals_get": (C.c_int, [C.c_void_p, C.POINTER(Totals)]),
+    "lbm_totals_get_static": (C.c_int, [C.c_void_p, C.POINTER(Totals)]),
     "lbm_fill_state_get": (C.c_int, [C.c_void_p, C.POINTER(FillQuery), C.POINTER(FillState)]),
     "lbm_get_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_set_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
