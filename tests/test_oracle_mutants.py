@@ -36,6 +36,8 @@ MUTANTS = [
     ("relaxation not weighted by 1 - n_s", "- (1.0 - nsx) / p->tau[s] * (fl[s][i] - feq)",
      "- 1.0 / p->tau[s] * (fl[s][i] - feq)", 1),
     ("bounce-back blend without 1 - n_s", "post[s][i] = (1.0 - nsx) * fl[s][i]", "post[s][i] = fl[s][i]", 1),
+    ("relaxation time off by one half", "- (1.0 - nsx) / p->tau[s] * (fl[s][i] - feq)",
+     "- (1.0 - nsx) / (p->tau[s] + 0.5) * (fl[s][i] - feq)", 1),
     ("second-order term of the equilibrium doubled", "(cu * cu) / (2.0 * CS2 * CS2)", "(cu * cu) / (CS2 * CS2)", 1),
     ("velocity term of the equilibrium halved", "1.0 + cu / CS2", "1.0 + cu / (2.0 * CS2)", 1),
     ("force shift without tau", "p->tau[s] * Ft[s][a] / rho_s[s]", "Ft[s][a] / rho_s[s]", 1),
