@@ -163,12 +163,14 @@ def ensemble(storage="f16s", ndom=64, steps=100, warmup=10, seed=3000):
 
 
 def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0, tile_x=0,
-            policy="fair", run_cells=0):
+            policy="fair", run_cells=0, conv_window=8):
     """Continuous-batching serving: Poisson arrivals at `rate` per second for
     `seconds`, each a porous domain of edge U{48..192} asking for U{2000..20000}
-    steps or convergence to 1e-6 relative momentum change; reports completion
-    latency percentiles and the aggregate MLUPS of the server under the given
-    sharing policy ("fair" or "shortest-first")."""
+    steps or convergence to 1e-6 relative change of its momentum, tested on
+    window means of `conv_window` samples (one per tick) with the noise floor
+    of the stochastically rounded state; reports completion latency
+    percentiles and the aggregate MLUPS of the server under the given sharing
+    policy ("fair" or "shortest-first")."""
     from paper_2206_11524_amd import inputs, lbm
 
     g = np.random.Generator(np.random.PCG64(seed))
@@ -202,7 +204,8 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
         while time.perf_counter() - t0 < ta:
             sample()
             time.sleep(0.002)
-        tickets.append(srv.submit_workload(w, steps, conv_tol=1e-6))
+        tickets.append(srv.submit_workload(w, steps, conv_tol=1e-6, conv_window=conv_window,
+                                           conv_noise=conv_window > 1))
         st = sample(force=True)
         depth = max(depth, st["queued"] + st["active"])
     # collect results, giving the queue drain_s after the last arrival to finish; a
@@ -230,8 +233,12 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
     srv.close()
     done = [r for r in res if r is not None and r["status"] == 0]
     lat = np.array([r["t_done"] - r["t_submit"] for r in done])
+    steps_asked = {k: s for k, (_, s) in enumerate(reqs)}
     return {"rate_per_s": rate, "arrival_window_s": seconds, "requests": len(reqs), "completed": len(done),
-            "converged": int(sum(r["converged"] for r in done)), "storage": storage, "policy": policy,
+            "converged": int(sum(r["converged"] for r in done)),
+            "steps_saved_by_convergence": int(sum(steps_asked[k] - r["steps_done"] for k, r in enumerate(res)
+                                                  if r is not None and r["status"] == 0 and r["converged"])),
+            "conv_window": conv_window, "storage": storage, "policy": policy,
             "mean_latency_s": round(float(lat.mean()), 3) if len(lat) else None,
             "p50_latency_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
             "p99_latency_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
@@ -305,6 +312,9 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=0.25, help="arrivals per second (0: no serving run)")
     ap.add_argument("--serve-seconds", type=float, default=40.0)
+    ap.add_argument("--serve-burst", type=int, default=24,
+                    help="also serve a burst of this many requests arriving within one second (0: none): the "
+                         "server saturated, as under the 20/s arrivals of the serving workload")
     ap.add_argument("--serve-drain", type=float, default=120.0,
                     help="seconds after the last arrival for the queue to finish")
     ap.add_argument("--serve-policy", default="fair", choices=("fair", "shortest-first"),
@@ -376,6 +386,11 @@ def main():
     if not args.no_ensemble:
         line["ensemble"] = ensemble()
         print(f"# ensemble: {line['ensemble']}", file=sys.stderr, flush=True)
+    if args.serve_burst > 0:
+        line["serving_saturated"] = serving(float(args.serve_burst), 1.0, drain_s=args.serve_drain,
+                                            tile_x=args.serve_tile, policy=args.serve_policy,
+                                            run_cells=args.serve_run_cells, seed=4500)
+        print(f"# serving (saturated): {line['serving_saturated']}", file=sys.stderr, flush=True)
     if args.serve_rate > 0:
         line["serving"] = serving(args.serve_rate, args.serve_seconds, drain_s=args.serve_drain,
                                   tile_x=args.serve_tile, policy=args.serve_policy,

@@ -286,15 +286,22 @@ void lbm_group_destroy(lbm_group* g);
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of simulation requests.
  *
- * A server owns a worker thread and a stream.  Requests (domain, n_s, initial
- * densities, parameters, step budget, convergence tolerance) are queued by
- * lbm_batch_submit from any thread.  Each tick the worker admits queued
- * requests while a slot is free and the resident state fits the HBM budget,
- * replays a captured graph of steps_per_tick batched launches over the
- * resident domains its policy steps (a domain that needs fewer steps stops
- * early), checks the FP64 momentum of each domain it stepped, and retires
- * those that reached their step
- * budget or converged.  Each result is the same as running the request alone.
+ * A server owns a worker thread and three streams (ticks, admissions,
+ * retirements; default priority).  Requests (domain, n_s, initial densities,
+ * parameters, step budget, convergence test) are queued by lbm_batch_submit
+ * from any thread.  The worker admits queued requests in arrival order while
+ * a slot is free and the resident state fits the HBM budget: their state gets
+ * a block of a device memory pool (grown in chunks up to the budget and kept),
+ * their arrays are uploaded and the state initialised on the admission
+ * stream while ticks run.  A tick replays a captured graph of steps_per_tick
+ * batched launches over the resident domains its policy steps (a domain that
+ * needs fewer steps stops early) and, for the domains with a convergence
+ * test, one batched FP64 reduction of their momentum.  Ticks are not waited
+ * for: the worker launches tick k, then reads tick k-1's reductions and
+ * retires what tick k-1 finished, while tick k runs.  A request whose test
+ * fires on tick k's state is therefore stepped by tick k+1 too (always
+ * exactly one tick more, alone or in a mix), and stops after it.  Each result
+ * is the same as running the request alone for the same number of steps.
  */
 typedef struct lbm_server lbm_server;
 
@@ -330,11 +337,21 @@ typedef struct {
     const double* rho_init;   /* [ncomp][N], copied at submit                                */
     lbm_params params;        /* storage, ncomp and c_ns must match the server               */
     int64_t max_steps;        /* run at most this many steps (>= 1)                          */
-    double conv_tol;          /* stop when |J(t) - J(t-K)| <= conv_tol |J(t)|, K = steps_per_tick;
-                                 0 disables.  With stochastic rounding J carries the rounding
-                                 noise of the 16-bit state, so the tolerance must lie above
-                                 it; with rounding to nearest the test also fires where the
-                                 rounded state stops changing before the flow has settled    */
+    double conv_tol;          /* convergence test on the state after each tick, 0 disables.
+                                 Sample: J = sum over cells of sum_s (1 - n_s)(j_s + F_ext,s/2),
+                                 the mixture momentum of Eq. (HMCSC_u_macro) without the
+                                 neighbour forces, FP64 on the device.  conv_window <= 1:
+                                 stop when |J(t) - J(t-K)| <= conv_tol |J(t)| (K =
+                                 steps_per_tick).  conv_window = W > 1: stop when the means of
+                                 the last two windows of W samples differ by at most conv_tol
+                                 times the newer one                                          */
+    int32_t conv_window;      /* samples per window, 0..1024 (0 and 1: consecutive samples)  */
+    int32_t conv_noise;       /* 1: with W > 1, also stop when the two window means differ by
+                                 at most twice the standard error of their difference (from
+                                 the spread within the windows): the state no longer drifts
+                                 beyond its own rounding noise.  A stochastically rounded
+                                 16-bit state carries noise of order 1e-4..1e-2 in J, far above
+                                 a tolerance of 1e-6, which alone would then never be met    */
     double* rho_out;          /* optional caller buffer [ncomp][N] for the final densities;
                                  must stay valid until the result is final                   */
 } lbm_request;
@@ -361,9 +378,10 @@ typedef struct {
 /* Create a server on the current device.  reserved must be NULL. */
 int lbm_server_create(const lbm_server_cfg* cfg, void* reserved, lbm_server** out);
 
-/* Queue a request; *ticket identifies it.  LBM_EINVAL for invalid input, a
- * format mismatch or LBM_FORCING_GUO, LBM_ENOMEM if its state can never fit the budget or it
- * exceeds max_cells. Thread-safe. */
+/* Queue a request; *ticket identifies it.  LBM_EINVAL for invalid input
+ * (including conv_window outside 0..1024, conv_noise not 0 or 1, non-finite
+ * densities), a format mismatch or LBM_FORCING_GUO, LBM_ENOMEM if its state can
+ * never fit the budget or it exceeds max_cells.  Thread-safe. */
 int lbm_batch_submit(lbm_server* s, const lbm_request* req, uint64_t* ticket);
 
 /* Result of a ticket: LBM_OK and *out filled when final, LBM_EAGAIN while

@@ -10,11 +10,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -284,6 +287,17 @@ void lbm_group_destroy(lbm_group* g) { delete g; }
 
 // ---------------------------------------------------------------------------
 // Server.
+//
+// The worker thread runs ticks back to back on the main stream without
+// waiting for them: it launches tick k, then waits for tick k-1 (already done
+// or about to be), reads that tick's convergence data, and retires what has
+// finished, while tick k runs.  A request's state lives in a block of a
+// device memory pool (grown in chunks up to the budget, never returned to the
+// device before the server ends).  Admission copies a request's arrays to
+// pinned staging, uploads them and initialises the state on a second stream,
+// overlapping the ticks; the request joins the ticks once that is done.
+// Retirement reads the final state on a third stream.  All streams have the
+// default priority.
 
 namespace {
 
@@ -295,32 +309,151 @@ struct Request {
     lbm_params prm{};
     int64_t max_steps = 0;
     double tol = 0.0;
+    int window = 1;
+    int noise = 0;
     double* rho_out = nullptr;
     double t_submit = 0.0;
     uint64_t bytes = 0;
 };
 
+// Device memory of the resident requests: chunks from hipMalloc, at most the
+// budget in total, allocated when first needed and kept; first-fit blocks,
+// neighbours merged on release.
+class DevicePool {
+  public:
+    void init(uint64_t budget, uint64_t chunk)
+    {
+        budget_ = budget;
+        chunk_ = chunk;
+    }
+    void* alloc(uint64_t bytes)
+    {
+        bytes = hm_rt::align_up(bytes);
+        for (Chunk& c : chunks_)
+            for (auto it = c.free.begin(); it != c.free.end(); ++it)
+                if (it->second >= bytes) {
+                    const uint64_t off = it->first, sz = it->second;
+                    c.free.erase(it);
+                    if (sz > bytes) c.free[off + bytes] = sz - bytes;
+                    return c.base + off;
+                }
+        if (reserved_ + bytes > budget_) return nullptr;
+        const uint64_t size = std::max(bytes, std::min(chunk_, budget_ - reserved_));
+        void* base = nullptr;
+        if (hipMalloc(&base, size) != hipSuccess) {
+            (void)hipGetLastError();
+            budget_ = reserved_;  // the device is full: stop growing
+            return nullptr;
+        }
+        reserved_ += size;
+        Chunk c;
+        c.base = static_cast<char*>(base);
+        c.size = size;
+        if (size > bytes) c.free[bytes] = size - bytes;
+        chunks_.push_back(std::move(c));
+        return base;
+    }
+    void release(void* p, uint64_t bytes)
+    {
+        bytes = hm_rt::align_up(bytes);
+        char* q = static_cast<char*>(p);
+        for (Chunk& c : chunks_) {
+            if (q < c.base || q >= c.base + c.size) continue;
+            uint64_t off = static_cast<uint64_t>(q - c.base), sz = bytes;
+            auto next = c.free.lower_bound(off);
+            if (next != c.free.end() && off + sz == next->first) {
+                sz += next->second;
+                next = c.free.erase(next);
+            }
+            if (next != c.free.begin()) {
+                auto prev = std::prev(next);
+                if (prev->first + prev->second == off) {
+                    off = prev->first;
+                    sz += prev->second;
+                    c.free.erase(prev);
+                }
+            }
+            c.free[off] = sz;
+            return;
+        }
+    }
+    void destroy()
+    {
+        for (Chunk& c : chunks_) (void)hipFree(c.base);
+        chunks_.clear();
+        reserved_ = 0;
+    }
+    uint64_t reserved() const { return reserved_; }
+
+  private:
+    struct Chunk {
+        char* base = nullptr;
+        uint64_t size = 0;
+        std::map<uint64_t, uint64_t> free;  // offset -> bytes
+    };
+    std::vector<Chunk> chunks_;
+    uint64_t budget_ = 0, chunk_ = 0, reserved_ = 0;
+};
+
 struct Slot {
     Request req;
     lbm_ctx* ctx = nullptr;
-    void* mem[3] = {nullptr, nullptr, nullptr};  // f_a, f_b, n_s
-    int64_t steps_done = 0;
-    double J_prev[3] = {0, 0, 0};
-    bool have_prev = false;
+    void* mem = nullptr;      // f_a | f_b | n_s in one pool block
+    uint64_t mem_bytes = 0;
+    int64_t issued = 0;       // steps launched
+    int64_t last_tick = -1;   // the last tick that stepped it
+    bool stop = false;        // converged or failed: no further ticks
+    bool converged = false;
+    int status = LBM_OK;
+    std::vector<std::array<double, 3>> hist;  // convergence monitor samples
     double t_admit = 0.0;
 };
+
+// What a tick launched: the slots it stepped and, for those it monitored,
+// their position in the tick's monitor output.
+struct TickRecord {
+    int64_t index = -1;
+    std::vector<Slot*> monitored;
+    hipEvent_t done = nullptr;
+};
+
+void ctx_release(lbm_ctx* c)
+{
+    if (!c) return;
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
 
 }  // namespace
 
 struct lbm_server {
     lbm_server_cfg cfg{};
     int device = 0;
-    hipStream_t stream = nullptr;
-    void* scratch = nullptr;
+    hipStream_t stream = nullptr;         // ticks and their monitors
+    hipStream_t admit_stream = nullptr;   // uploads and initial states
+    hipStream_t retire_stream = nullptr;  // final moments
+    void* scratch = nullptr;              // FP64 fields and reductions of retirements
     uint64_t scratch_bytes = 0;
     uint64_t budget = 0;
+    DevicePool pool;
     BatchRunner runner;
     std::chrono::steady_clock::time_point t0;
+
+    // admission staging: pinned host arrays and the device densities
+    char* stage_host = nullptr;
+    double* stage_rho = nullptr;
+    hipEvent_t admit_done = nullptr;
+    std::unique_ptr<Slot> admitting;
+
+    // convergence monitor: tables, partial sums and outputs per tick parity
+    void* mon_dev[2] = {nullptr, nullptr};
+    char* mon_host[2] = {nullptr, nullptr};
+    double* mon_part = nullptr;
+    double* mon_out_dev[2] = {nullptr, nullptr};
+    double* mon_out_host[2] = {nullptr, nullptr};
+    size_t mon_bytes = 0;
+    TickRecord rec[2];
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -332,8 +465,9 @@ struct lbm_server {
     std::thread worker;
 
     // worker-owned
-    std::vector<Slot> active;
+    std::vector<std::unique_ptr<Slot>> active;
     std::vector<hm::BatchDomain> doms;
+    std::vector<hm::MonitorDomain> mdoms;
     uint64_t resident = 0;
 
     // statistics (guarded by mu)
@@ -341,8 +475,11 @@ struct lbm_server {
     double busy_since = -1.0;
 
     void run();
-    int admit(Request&& r);
+    bool start_admission();
+    bool finish_admission(bool block);
+    void process_tick(TickRecord& r, int parity);
     void retire(size_t i, int status, bool converged);
+    void fail_request(Request& r, int status);
 };
 
 namespace {
@@ -354,55 +491,208 @@ uint64_t state_bytes(const lbm_domain& d, const lbm_params& p)
     return 2 * s.pop_bytes + s.ns_bytes;
 }
 
+// Convergence of one monitored request after a new sample J (the local
+// mixture momentum of its state): with a window of 1, |J - J_prev| <= tol |J|
+// over the last two samples; with a window W > 1, the means of the last two
+// windows of W samples differ by at most tol times the newer mean, or (noise
+// floor on) by at most twice the standard error of their difference estimated
+// from the spread within the windows (the state no longer drifts beyond its
+// own rounding noise).
+bool converged_now(const Slot& s)
+{
+    const int W = std::max(1, s.req.window);
+    const size_t n = s.hist.size();
+    if (n < static_cast<size_t>(2 * W)) return false;
+    double m1[3] = {0, 0, 0}, m0[3] = {0, 0, 0};
+    for (int k = 0; k < W; ++k)
+        for (int a = 0; a < 3; ++a) {
+            m1[a] += s.hist[n - 1 - k][a] / W;
+            m0[a] += s.hist[n - 1 - W - k][a] / W;
+        }
+    double d2 = 0, n2 = 0;
+    for (int a = 0; a < 3; ++a) {
+        d2 += (m1[a] - m0[a]) * (m1[a] - m0[a]);
+        n2 += m1[a] * m1[a];
+    }
+    if (std::sqrt(d2) <= s.req.tol * std::sqrt(n2)) return true;
+    if (!s.req.noise || W < 2) return false;
+    double v1 = 0, v0 = 0;
+    for (int k = 0; k < W; ++k)
+        for (int a = 0; a < 3; ++a) {
+            v1 += (s.hist[n - 1 - k][a] - m1[a]) * (s.hist[n - 1 - k][a] - m1[a]);
+            v0 += (s.hist[n - 1 - W - k][a] - m0[a]) * (s.hist[n - 1 - W - k][a] - m0[a]);
+        }
+    const double se2 = (v1 + v0) / (W - 1) / W;
+    return d2 <= 4.0 * se2;
+}
+
 }  // namespace
 
-int lbm_server::admit(Request&& r)
+void lbm_server::fail_request(Request& r, int status)
 {
-    Slot sl;
-    sl.req = std::move(r);
+    lbm_result res{};
+    res.status = status;
+    res.t_submit = r.t_submit;
+    res.t_done = now_s(t0);
+    std::lock_guard<std::mutex> lk(mu);
+    done[r.id] = res;
+    live.erase(r.id);
+    st.completed += 1;
+    cv_done.notify_all();
+}
+
+// Take the next queued request into the admission stage if a slot and pool
+// memory are free: upload its arrays and initialise its state on the
+// admission stream.  Returns true if an admission started.
+bool lbm_server::start_admission()
+{
+    if (admitting) return false;
+    Request r;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (queue.empty() || static_cast<int>(active.size()) >= cfg.max_slots) return false;
+        if (resident + queue.front().bytes > budget) return false;
+        r = std::move(queue.front());
+        queue.pop_front();
+        st.queued = static_cast<int64_t>(queue.size());
+    }
     lbm_sizes sz{};
-    lbm_required_bytes(&sl.req.dom, &sl.req.prm, &sz);
-    if (hipMalloc(&sl.mem[0], sz.pop_bytes) != hipSuccess || hipMalloc(&sl.mem[1], sz.pop_bytes) != hipSuccess ||
-        hipMalloc(&sl.mem[2], sz.ns_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        for (void* m : sl.mem)
-            if (m) (void)hipFree(m);
-        return LBM_ENOMEM;
+    lbm_required_bytes(&r.dom, &r.prm, &sz);
+    const uint64_t total = sz.pop_bytes * 2 + sz.ns_bytes;
+    void* mem = pool.alloc(total);
+    if (!mem) {  // fragmented or the device is full: wait for a retirement
+        std::lock_guard<std::mutex> lk(mu);
+        queue.push_front(std::move(r));
+        st.queued = static_cast<int64_t>(queue.size());
+        return false;
     }
-    lbm_device_buffers b{sl.mem[0], sl.mem[1], sl.mem[2], scratch};
-    const int rc = lbm_create(&sl.req.dom, sl.req.ns.data(), sl.req.rho.data(), &sl.req.prm, &b, stream, &sl.ctx);
+    std::unique_ptr<Slot> sl(new Slot());
+    sl->req = std::move(r);
+    sl->mem = mem;
+    sl->mem_bytes = total;
+    char* m = static_cast<char*>(mem);
+    lbm_device_buffers b{m, m + sz.pop_bytes, m + 2 * sz.pop_bytes, scratch};
+    int rc = hm_rt::ctx_bind(&sl->req.dom, &sl->req.prm, &b, stream, &sl->ctx);
+    const int64_t N = sl->ctx ? sl->ctx->prob.N : 0;
+    const size_t ns_b = sizeof(float) * static_cast<size_t>(sl->req.prm.c_ns) * N;
+    const size_t rho_b = sizeof(double) * static_cast<size_t>(sl->req.prm.ncomp) * N;
+    if (rc == LBM_OK) {
+        std::memcpy(stage_host, sl->req.rho.data(), rho_b);
+        std::memcpy(stage_host + hm_rt::align_up(rho_b), sl->req.ns.data(), ns_b);
+        if (hipMemcpyAsync(stage_rho, stage_host, rho_b, hipMemcpyHostToDevice, admit_stream) != hipSuccess ||
+            hipMemcpyAsync(sl->ctx->ns, stage_host + hm_rt::align_up(rho_b), ns_b, hipMemcpyHostToDevice,
+                           admit_stream) != hipSuccess ||
+            hm::launch_init(sl->ctx->prob, stage_rho, sl->ctx->buf[0], admit_stream) != hipSuccess ||
+            hipEventRecord(admit_done, admit_stream) != hipSuccess)
+            rc = LBM_EDEVICE;
+    }
     if (rc) {
-        for (void* m : sl.mem)
-            if (m) (void)hipFree(m);
-        return rc;
+        ctx_release(sl->ctx);
+        pool.release(mem, total);
+        fail_request(sl->req, rc);
+        return false;
     }
-    sl.req.ns.clear();
-    sl.req.ns.shrink_to_fit();
-    sl.req.rho.clear();
-    sl.req.rho.shrink_to_fit();
-    sl.t_admit = now_s(t0);
-    resident += sl.req.bytes;
-    active.push_back(std::move(sl));
-    return LBM_OK;
+    sl->req.ns.clear();
+    sl->req.ns.shrink_to_fit();
+    sl->req.rho.clear();
+    sl->req.rho.shrink_to_fit();
+    sl->t_admit = now_s(t0);
+    resident += sl->req.bytes;
+    admitting = std::move(sl);
+    return true;
+}
+
+// Move the admitted request into the resident set once its state is ready
+// (waiting for it if block).  Returns true if it joined.
+bool lbm_server::finish_admission(bool block)
+{
+    if (!admitting) return false;
+    const hipError_t e = block ? hipEventSynchronize(admit_done) : hipEventQuery(admit_done);
+    if (e == hipErrorNotReady) return false;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        Slot* s = admitting.get();
+        resident -= s->req.bytes;
+        ctx_release(s->ctx);
+        pool.release(s->mem, s->mem_bytes);
+        fail_request(s->req, LBM_EDEVICE);
+        admitting.reset();
+        return false;
+    }
+    active.push_back(std::move(admitting));
+    return true;
+}
+
+// Read the convergence samples of a finished tick.
+void lbm_server::process_tick(TickRecord& r, int parity)
+{
+    if (r.index < 0) return;
+    if (hipEventSynchronize(r.done) != hipSuccess) {
+        (void)hipGetLastError();
+        for (Slot* s : r.monitored) {
+            s->stop = true;
+            s->status = LBM_EDEVICE;
+        }
+    } else {
+        for (size_t k = 0; k < r.monitored.size(); ++k) {
+            Slot* s = r.monitored[k];
+            const double* o = mon_out_host[parity] + 4 * k;
+            if (!(std::isfinite(o[0]) && std::isfinite(o[1]) && std::isfinite(o[2]) && std::isfinite(o[3]))) {
+                s->stop = true;
+                s->status = LBM_EUNSTABLE;
+                continue;
+            }
+            s->hist.push_back({o[0], o[1], o[2]});
+            if (s->hist.size() > static_cast<size_t>(4 * std::max(1, s->req.window)))
+                s->hist.erase(s->hist.begin());
+            if (converged_now(*s)) {
+                s->stop = true;
+                s->converged = true;
+            }
+        }
+    }
+    r.monitored.clear();
+    r.index = -1;
 }
 
 void lbm_server::retire(size_t i, int status, bool converged)
 {
-    Slot& sl = active[i];
+    Slot& sl = *active[i];
     lbm_result res{};
     res.status = status;
     res.converged = converged ? 1 : 0;
-    res.steps_done = sl.steps_done;
+    res.steps_done = sl.issued;
     res.t_submit = sl.req.t_submit;
     res.t_admit = sl.t_admit;
     if (status == LBM_OK) {
-        const int rc = lbm_moments(sl.ctx, sl.req.rho_out, nullptr, nullptr, &res.totals);
-        if (rc) res.status = rc;
+        // final FP64 moments, as lbm_moments computes them, on the retire stream
+        lbm_ctx* c = sl.ctx;
+        double* rho = reinterpret_cast<double*>(c->scratch + c->sl.rho);
+        double* part = reinterpret_cast<double*>(c->scratch + c->sl.partials);
+        double* tots = reinterpret_cast<double*>(c->scratch + c->sl.totals);
+        double h[5];
+        if (hm::launch_diagnostics(c->prob, c->buf[c->cur], c->ns, true, rho, nullptr, nullptr, part, tots,
+                                   retire_stream) != hipSuccess ||
+            hipMemcpyAsync(h, tots, sizeof(h), hipMemcpyDeviceToHost, retire_stream) != hipSuccess ||
+            (sl.req.rho_out &&
+             hipMemcpyAsync(sl.req.rho_out, rho, sizeof(double) * c->prm.ncomp * c->prob.N, hipMemcpyDeviceToHost,
+                            retire_stream) != hipSuccess) ||
+            hipStreamSynchronize(retire_stream) != hipSuccess) {
+            (void)hipGetLastError();
+            res.status = LBM_EDEVICE;
+        } else {
+            res.totals.mass[0] = h[0];
+            res.totals.mass[1] = c->prm.ncomp == 2 ? h[1] : 0.0;
+            for (int a = 0; a < 3; ++a) res.totals.momentum[a] = h[2 + a];
+            res.totals.time = c->t;
+            int fin = 1;
+            for (double v : h) fin &= std::isfinite(v) ? 1 : 0;
+            res.totals.finite = fin;
+        }
     }
     res.t_done = now_s(t0);
-    lbm_destroy(sl.ctx);
-    for (void* m : sl.mem)
-        if (m) (void)hipFree(m);
+    ctx_release(sl.ctx);
+    pool.release(sl.mem, sl.mem_bytes);
     resident -= sl.req.bytes;
     const uint64_t id = sl.req.id;
     active.erase(active.begin() + static_cast<long>(i));
@@ -420,11 +710,12 @@ void lbm_server::retire(size_t i, int status, bool converged)
 void lbm_server::run()
 {
     (void)hipSetDevice(device);
+    int64_t tick = 0;
     for (;;) {
-        std::vector<Request> admitted;
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (active.empty() && queue.empty() && !stop) {
+            const bool idle = active.empty() && !admitting && queue.empty() && rec[0].index < 0 && rec[1].index < 0;
+            if (idle && !stop) {
                 if (busy_since >= 0) {
                     st.busy_seconds += now_s(t0) - busy_since;
                     busy_since = -1.0;
@@ -432,108 +723,112 @@ void lbm_server::run()
                 cv_work.wait_for(lk, std::chrono::milliseconds(20));
             }
             if (stop) break;
-            // admission: in arrival order while a slot is free and the state fits
-            uint64_t planned = resident;
-            while (!queue.empty() && static_cast<int>(active.size() + admitted.size()) < cfg.max_slots &&
-                   planned + queue.front().bytes <= budget) {
-                planned += queue.front().bytes;
-                admitted.push_back(std::move(queue.front()));
-                queue.pop_front();
-            }
-            st.queued = static_cast<int64_t>(queue.size());
+            if (busy_since < 0 && (!active.empty() || admitting || !queue.empty())) busy_since = now_s(t0);
         }
-        for (Request& r : admitted) {
-            const uint64_t id = r.id;
-            const double ts = r.t_submit;
-            const int rc = admit(std::move(r));
-            if (rc) {
-                lbm_result res{};
-                res.status = rc;
-                res.t_submit = ts;
-                res.t_done = now_s(t0);
-                std::lock_guard<std::mutex> lk(mu);
-                done[id] = res;
-                live.erase(id);
-                st.completed += 1;
-                cv_done.notify_all();
-            }
-        }
-        if (active.empty()) continue;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            if (busy_since < 0) busy_since = now_s(t0);
-            st.active = static_cast<int64_t>(active.size());
-            st.bytes_resident = resident;
-        }
-        // one tick: K launches over the resident domains this tick steps
+        // one tick over the resident requests that have steps left
         const int K = runner.kmax();
-        std::vector<int> steps(active.size());
-        for (size_t i = 0; i < active.size(); ++i)
-            steps[i] = static_cast<int>(std::min<int64_t>(K, active[i].req.max_steps - active[i].steps_done));
+        const int par = static_cast<int>(tick & 1);
+        std::vector<int> steps(active.size(), 0);
+        for (size_t i = 0; i < active.size(); ++i) {
+            const Slot& s = *active[i];
+            if (!s.stop) steps[i] = static_cast<int>(std::min<int64_t>(K, s.req.max_steps - s.issued));
+        }
         if (cfg.policy == LBM_SERVE_SHORTEST_FIRST) {
-            std::vector<size_t> order(active.size());
-            std::vector<double> work(active.size());
-            for (size_t i = 0; i < active.size(); ++i) {
-                order[i] = i;
-                work[i] = static_cast<double>(active[i].ctx->prob.N) *
-                          static_cast<double>(active[i].req.max_steps - active[i].steps_done);
-            }
-            std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work[a] < work[b]; });
+            std::vector<size_t> order;
+            for (size_t i = 0; i < active.size(); ++i)
+                if (steps[i] > 0) order.push_back(i);
+            std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+                const Slot &sa = *active[a], &sb = *active[b];
+                return static_cast<double>(sa.ctx->prob.N) * static_cast<double>(sa.req.max_steps - sa.issued) <
+                       static_cast<double>(sb.ctx->prob.N) * static_cast<double>(sb.req.max_steps - sb.issued);
+            });
             int64_t stepped = 0;
             for (size_t i : order) {
                 if (stepped >= cfg.run_cells) steps[i] = 0;
-                else stepped += active[i].ctx->prob.N;
+                else stepped += active[i]->ctx->prob.N;
             }
         }
         doms.clear();
+        mdoms.clear();
+        std::vector<Slot*> monitored;
         double cells = 0.0;
         for (size_t i = 0; i < active.size(); ++i) {
             if (!steps[i]) continue;
-            doms.push_back(domain_of(active[i].ctx, steps[i]));
-            cells += static_cast<double>(active[i].ctx->prob.N) * steps[i];
+            Slot& s = *active[i];
+            doms.push_back(domain_of(s.ctx, steps[i]));
+            cells += static_cast<double>(s.ctx->prob.N) * steps[i];
         }
-        int rc = runner.run(doms.data(), static_cast<int>(doms.size()), K);
-        if (rc == LBM_OK && hipStreamSynchronize(stream) != hipSuccess) rc = LBM_EDEVICE;
-        for (size_t i = 0; i < active.size(); ++i) {
-            advance(active[i].ctx, steps[i]);
-            active[i].steps_done += steps[i];
-        }
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            st.cell_updates += cells;
-            st.ticks += 1;
-        }
-        // retire finished, converged or failed domains
-        for (size_t i = active.size(); i-- > 0;) {
-            Slot& sl = active[i];
-            if (rc) {
-                retire(i, rc, false);
-                continue;
-            }
-            if (sl.steps_done >= sl.req.max_steps) {
-                retire(i, LBM_OK, false);
-                continue;
-            }
-            if (sl.req.tol > 0.0 && steps[i] > 0) {
-                lbm_totals tt{};
-                const int trc = lbm_totals_get(sl.ctx, &tt);
-                if (trc || !tt.finite) {
-                    retire(i, trc ? trc : LBM_EUNSTABLE, false);
-                    continue;
+        int rc = LBM_OK;
+        if (!doms.empty()) {
+            rc = runner.run(doms.data(), static_cast<int>(doms.size()), K);
+            for (size_t i = 0; i < active.size(); ++i) {
+                if (!steps[i]) continue;
+                Slot& s = *active[i];
+                advance(s.ctx, steps[i]);
+                s.issued += steps[i];
+                s.last_tick = tick;
+                if (s.req.tol > 0.0) {
+                    monitored.push_back(&s);
+                    mdoms.push_back({s.ctx->prob, s.ctx->buf[s.ctx->cur], s.ctx->ns});
                 }
-                const double nJ = std::sqrt(tt.momentum[0] * tt.momentum[0] + tt.momentum[1] * tt.momentum[1] +
-                                            tt.momentum[2] * tt.momentum[2]);
-                double dJ = 0.0;
-                for (int a = 0; a < 3; ++a) dJ += (tt.momentum[a] - sl.J_prev[a]) * (tt.momentum[a] - sl.J_prev[a]);
-                dJ = std::sqrt(dJ);
-                const bool conv = sl.have_prev && dJ <= sl.req.tol * nJ;
-                for (int a = 0; a < 3; ++a) sl.J_prev[a] = tt.momentum[a];
-                sl.have_prev = true;
-                if (conv) retire(i, LBM_OK, true);
             }
+            if (rc == LBM_OK && !mdoms.empty()) {
+                // the monitor table of the other parity's tick is no longer read
+                const int blocks = hm::monitor_encode(cfg.storage, mdoms.data(), static_cast<int>(mdoms.size()),
+                                                      mon_host[par]);
+                if (hipMemcpyAsync(mon_dev[par], mon_host[par], mon_bytes, hipMemcpyHostToDevice, stream) !=
+                        hipSuccess ||
+                    hm::launch_monitor(cfg.storage, mon_dev[par], static_cast<int>(mdoms.size()), blocks, mon_part,
+                                       mon_out_dev[par], stream) != hipSuccess ||
+                    hipMemcpyAsync(mon_out_host[par], mon_out_dev[par], sizeof(double) * 4 * mdoms.size(),
+                                   hipMemcpyDeviceToHost, stream) != hipSuccess)
+                    rc = LBM_EDEVICE;
+            }
+            if (rc == LBM_OK && hipEventRecord(rec[par].done, stream) != hipSuccess) rc = LBM_EDEVICE;
+            rec[par].index = tick;
+            rec[par].monitored = std::move(monitored);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                st.cell_updates += cells;
+                st.ticks += 1;
+                st.active = static_cast<int64_t>(active.size());
+                st.bytes_resident = resident;
+            }
+            ++tick;
+        }
+        if (rc) {
+            (void)hipStreamSynchronize(stream);
+            for (auto& s : active) {
+                s->stop = true;
+                if (s->status == LBM_OK) s->status = rc;
+            }
+        }
+        // admissions while the tick runs (uploads and initial states on the
+        // admission stream): every queued request that has a slot and fits
+        // joins the next tick
+        for (int k = 0; k < cfg.max_slots && start_admission(); ++k) finish_admission(true);
+        // the previous tick (or, with nothing launched now, the last one): its
+        // convergence samples, then every request whose final state it holds
+        const int prev = doms.empty() ? par ^ 1 : par ^ 1;
+        int64_t completed = -1;
+        if (rec[prev].index >= 0) {
+            completed = rec[prev].index;
+            process_tick(rec[prev], prev);
+        }
+        if (doms.empty() && rec[par].index >= 0) {
+            completed = rec[par].index;
+            process_tick(rec[par], par);
+        }
+        for (size_t i = active.size(); i-- > 0;) {
+            Slot& s = *active[i];
+            const bool finished = s.stop || s.issued >= s.req.max_steps;
+            if (finished && s.last_tick <= completed) retire(i, s.status, s.converged);
         }
     }
-    // shutting down: everything still queued or resident ends unfinished
+    // shutting down: everything resident ends unfinished
+    (void)hipStreamSynchronize(stream);
+    (void)hipStreamSynchronize(admit_stream);
+    if (admitting) active.push_back(std::move(admitting));
     for (size_t i = active.size(); i-- > 0;) retire(i, LBM_EAGAIN, false);
 }
 
@@ -562,28 +857,46 @@ int lbm_server_create(const lbm_server_cfg* cfg, void* reserved, lbm_server** ou
     s->cfg.tile_y = ty;
     if (!s->cfg.run_cells) s->cfg.run_cells = int64_t(1) << 24;
     s->t0 = std::chrono::steady_clock::now();
-    if (hipGetDevice(&s->device) != hipSuccess || hipStreamCreate(&s->stream) != hipSuccess) {
-        delete s;
-        return LBM_EDEVICE;
-    }
+    auto fail = [&](int rc) {
+        lbm_server_destroy(s);
+        return rc;
+    };
+    if (hipGetDevice(&s->device) != hipSuccess || hipStreamCreate(&s->stream) != hipSuccess ||
+        hipStreamCreate(&s->admit_stream) != hipSuccess || hipStreamCreate(&s->retire_stream) != hipSuccess ||
+        hipEventCreateWithFlags(&s->admit_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->rec[0].done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->rec[1].done, hipEventDisableTiming) != hipSuccess)
+        return fail(LBM_EDEVICE);
     s->scratch_bytes = hm_rt::scratch_layout(cfg->max_cells, cfg->ncomp).bytes;
-    if (hipMalloc(&s->scratch, s->scratch_bytes) != hipSuccess) {
-        (void)hipStreamDestroy(s->stream);
-        delete s;
-        return LBM_ENOMEM;
+    const size_t rho_b = hm_rt::align_up(sizeof(double) * cfg->ncomp * static_cast<size_t>(cfg->max_cells));
+    const size_t ns_b = hm_rt::align_up(sizeof(float) * cfg->c_ns * static_cast<size_t>(cfg->max_cells));
+    s->mon_bytes = hm::monitor_table_bytes(cfg->storage, cfg->max_slots);
+    if (hipMalloc(&s->scratch, s->scratch_bytes) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&s->stage_rho), rho_b) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s->stage_host), rho_b + ns_b, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&s->mon_part),
+                  sizeof(double) * 4 * hm::monitor_max_blocks(cfg->max_slots)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_ENOMEM);
     }
+    for (int j = 0; j < 2; ++j)
+        if (hipMalloc(&s->mon_dev[j], s->mon_bytes) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&s->mon_host[j]), s->mon_bytes, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&s->mon_out_dev[j]), sizeof(double) * 4 * cfg->max_slots) !=
+                hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&s->mon_out_host[j]), sizeof(double) * 4 * cfg->max_slots,
+                          hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM);
+        }
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     s->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : static_cast<uint64_t>(0.9 * free_b);
+    s->pool.init(s->budget, uint64_t(8) << 30);
     const int rc = s->runner.init(cfg->storage, cfg->ncomp, cfg->c_ns, tx, ty, cfg->max_slots, cfg->steps_per_tick,
                                   s->stream);
-    if (rc) {
-        s->runner.release();
-        (void)hipFree(s->scratch);
-        (void)hipStreamDestroy(s->stream);
-        delete s;
-        return rc;
-    }
+    if (rc) return fail(rc);
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return LBM_OK;
@@ -596,6 +909,8 @@ int lbm_batch_submit(lbm_server* s, const lbm_request* rq, uint64_t* ticket)
     const lbm_params& p = rq->params;
     if (p.storage != s->cfg.storage || p.ncomp != s->cfg.ncomp || p.c_ns != s->cfg.c_ns) return LBM_EINVAL;
     if (rq->max_steps < 1 || !(rq->conv_tol >= 0.0) || !rq->n_s || !rq->rho_init) return LBM_EINVAL;
+    if (rq->conv_window < 0 || rq->conv_window > 1024 || (rq->conv_noise != 0 && rq->conv_noise != 1))
+        return LBM_EINVAL;
     if (p.check_every != 0) return LBM_EINVAL;
     if (p.forcing != LBM_FORCING_SHAN_CHEN) return LBM_EINVAL;  // the batched kernel runs the HMCSC only
     lbm_sizes sz{};
@@ -608,6 +923,8 @@ int lbm_batch_submit(lbm_server* s, const lbm_request* rq, uint64_t* ticket)
     r.prm = p;
     r.max_steps = rq->max_steps;
     r.tol = rq->conv_tol;
+    r.window = std::max(1, static_cast<int>(rq->conv_window));
+    r.noise = rq->conv_noise;
     r.rho_out = rq->rho_out;
     r.bytes = state_bytes(rq->dom, p);
     if (r.bytes > s->budget) return LBM_ENOMEM;
@@ -615,6 +932,8 @@ int lbm_batch_submit(lbm_server* s, const lbm_request* rq, uint64_t* ticket)
     r.rho.assign(rq->rho_init, rq->rho_init + static_cast<size_t>(p.ncomp) * N);
     for (float v : r.ns)
         if (!(v >= 0.0f && v <= 1.0f)) return LBM_EINVAL;
+    for (double v : r.rho)
+        if (!std::isfinite(v)) return LBM_EINVAL;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return LBM_EINVAL;
@@ -689,8 +1008,23 @@ void lbm_server_destroy(lbm_server* s)
     if (s->worker.joinable()) s->worker.join();
     s->cv_done.notify_all();
     s->runner.release();
+    for (hipStream_t q : {s->stream, s->admit_stream, s->retire_stream})
+        if (q) (void)hipStreamSynchronize(q);
+    s->pool.destroy();
     if (s->scratch) (void)hipFree(s->scratch);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->stage_rho) (void)hipFree(s->stage_rho);
+    if (s->stage_host) (void)hipHostFree(s->stage_host);
+    if (s->mon_part) (void)hipFree(s->mon_part);
+    for (int j = 0; j < 2; ++j) {
+        if (s->mon_dev[j]) (void)hipFree(s->mon_dev[j]);
+        if (s->mon_host[j]) (void)hipHostFree(s->mon_host[j]);
+        if (s->mon_out_dev[j]) (void)hipFree(s->mon_out_dev[j]);
+        if (s->mon_out_host[j]) (void)hipHostFree(s->mon_out_host[j]);
+        if (s->rec[j].done) (void)hipEventDestroy(s->rec[j].done);
+    }
+    if (s->admit_done) (void)hipEventDestroy(s->admit_done);
+    for (hipStream_t q : {s->stream, s->admit_stream, s->retire_stream})
+        if (q) (void)hipStreamDestroy(q);
     delete s;
 }
 

@@ -60,6 +60,10 @@ struct lbm_ctx {
 };
 
 namespace hm_rt {
+// A context over caller buffers, without any device work (see lbm_runtime.cpp).
+int ctx_bind(const lbm_domain* dom, const lbm_params* prm, const lbm_device_buffers* bufs, hipStream_t stream,
+             lbm_ctx** out);
+
 // FP64 totals (and, if fields, per-cell moments into scratch) of the current
 // state.  With forces false only the mass and the local part of the momentum
 // are summed (the health check).

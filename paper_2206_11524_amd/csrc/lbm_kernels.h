@@ -136,4 +136,28 @@ int batch_blocks_per_cu(int storage, int ncomp, int c_ns, int tile_x, int tile_y
 hipError_t launch_step_batch(int storage, int ncomp, int c_ns, int tile_x, int tile_y, const void* table, int k,
                              int grid, hipStream_t st);
 
+// Convergence monitor (server): one domain of a monitor table.
+struct MonitorDomain {
+    Problem prob;
+    const void* state;  // buffer holding the state to monitor
+    const float* ns;
+};
+
+constexpr int kMonitorBlocksPerDomain = 256;
+
+// Size of a device monitor table for up to max_domains domains, and the
+// most blocks (partials of 4 doubles each) its launch uses.
+size_t monitor_table_bytes(int storage, int max_domains);
+int monitor_max_blocks(int max_domains);
+
+// Encode the table for n domains into host memory; returns the total number
+// of blocks of the launch.
+int monitor_encode(int storage, const MonitorDomain* d, int n, void* host);
+
+// For each domain d of the (device) table: out[4 d .. 4 d + 3] = {sum over
+// cells of sum_s (1 - n_s)(j_s + F_ext,s / 2) (x, y, z), sum of rho}, FP64,
+// deterministic.  partials holds 4 * total_blocks doubles.
+hipError_t launch_monitor(int storage, const void* table, int ndom, int total_blocks, double* partials, double* out,
+                          hipStream_t st);
+
 }  // namespace hm

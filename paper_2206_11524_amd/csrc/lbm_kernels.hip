@@ -2350,6 +2350,153 @@ hipError_t launch_fill(const Problem& p, const FillQuery& q, const double* rho, 
 }
 
 // ---------------------------------------------------------------------------
+// Convergence monitor of the server: for every domain of a table, the FP64
+// sums over its cells of the local part of rho u_macro (Eq. HMCSC_u_macro
+// without the neighbour forces), sum_s (1 - n_s)(j_s + F_ext,s / 2), and of
+// the mass.  One launch covers all domains (each owns a run of blocks); a
+// second launch reduces each domain's blocks in a fixed order.
+template <typename T>
+struct MonitorEntry {
+    Args<T> a;
+    const void* state;
+    const float* ns;
+    int ncomp, c_ns;
+    int block_begin, nblocks;
+};
+
+struct MonitorHeader {
+    int ndom;
+    int total_blocks;
+    int pad[2];
+};
+
+template <typename ST>
+__global__ __launch_bounds__(kRedThreads) void k_monitor(const char* __restrict__ table, double* __restrict__ partials)
+{
+    using T = typename ST::T;
+    const MonitorHeader* hdr = reinterpret_cast<const MonitorHeader*>(table);
+    const MonitorEntry<T>* ent = reinterpret_cast<const MonitorEntry<T>*>(table + kBatchEntryOffset);
+    const int b = blockIdx.x;
+    int lo = 0, hi = hdr->ndom - 1;  // last domain with block_begin <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].block_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const MonitorEntry<T>& e = ent[lo];
+    const Args<T>& a = e.a;
+    const typename ST::E* A = static_cast<const typename ST::E*>(e.state);
+    double acc[4] = {0, 0, 0, 0};
+    const int64_t stride = static_cast<int64_t>(e.nblocks) * blockDim.x;
+    for (int64_t n = static_cast<int64_t>(b - e.block_begin) * blockDim.x + threadIdx.x; n < a.N; n += stride) {
+        const Cell c = cell_of(a, n);
+        const int res = reservoir_of(a, c.x, c.y, c.z);
+        const int xs[3] = {wrap_inc(c.x, a.nx), c.x, wrap_dec(c.x, a.nx)};
+        const int ys[3] = {wrap_inc(c.y, a.ny), c.y, wrap_dec(c.y, a.ny)};
+        const int zs[3] = {wrap_inc(c.z, a.nz), c.z, wrap_dec(c.z, a.nz)};
+        double rs[2] = {0, 0}, j[2][3] = {{0, 0, 0}, {0, 0, 0}}, rtot = 0;
+        for (int s = 0; s < e.ncomp; ++s) {
+            double d = 0;
+            if (res >= 0) {
+                d = static_cast<double>(a.res_dr[res][s]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    const double h = static_cast<double>(
+                        ST::dec(A[pidx(a, s, i, zs[CZ[i] + 1], ys[CY[i] + 1] * a.nx + xs[CX[i] + 1])], a.inv_scale));
+                    d += h;
+                    j[s][0] += CX[i] * h;
+                    j[s][1] += CY[i] * h;
+                    j[s][2] += CZ[i] * h;
+                }
+            }
+            rs[s] = static_cast<double>(a.rho0[s]) + d;
+            rtot += rs[s];
+        }
+        for (int s = 0; s < e.ncomp; ++s) {
+            const double wfl = 1.0 - static_cast<double>(e.ns[static_cast<size_t>(e.c_ns == 2 ? s : 0) * a.N + n]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double fext = rtot > 0 ? rs[s] / rtot * static_cast<double>(a.F[d]) : 0.0;
+                acc[d] += wfl * (j[s][d] + fext / 2.0);
+            }
+        }
+        acc[3] += rtot;
+    }
+    block_sum<4>(acc, partials + static_cast<size_t>(b) * 4);
+}
+
+template <typename ST>
+__global__ __launch_bounds__(kRedThreads) void k_monitor_reduce(const char* __restrict__ table,
+                                                                const double* __restrict__ partials,
+                                                                double* __restrict__ out)
+{
+    using T = typename ST::T;
+    const MonitorEntry<T>* ent = reinterpret_cast<const MonitorEntry<T>*>(table + kBatchEntryOffset);
+    const MonitorEntry<T>& e = ent[blockIdx.x];
+    double acc[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < e.nblocks; b += kRedThreads)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += partials[static_cast<size_t>(e.block_begin + b) * 4 + k];
+    block_sum<4>(acc, out + static_cast<size_t>(blockIdx.x) * 4);
+}
+
+template <typename T>
+static size_t monitor_bytes_t(int max_domains)
+{
+    return kBatchEntryOffset + sizeof(MonitorEntry<T>) * static_cast<size_t>(max_domains > 0 ? max_domains : 1);
+}
+
+size_t monitor_table_bytes(int storage, int max_domains)
+{
+    return storage == kF64 ? monitor_bytes_t<double>(max_domains) : monitor_bytes_t<float>(max_domains);
+}
+
+int monitor_max_blocks(int max_domains) { return kMonitorBlocksPerDomain * (max_domains > 0 ? max_domains : 1); }
+
+template <typename T>
+static int monitor_encode_t(const MonitorDomain* d, int n, void* host)
+{
+    MonitorHeader* h = static_cast<MonitorHeader*>(host);
+    MonitorEntry<T>* e = reinterpret_cast<MonitorEntry<T>*>(static_cast<char*>(host) + kBatchEntryOffset);
+    int blocks = 0;
+    for (int i = 0; i < n; ++i) {
+        e[i].a = make_args<T>(d[i].prob);
+        e[i].state = d[i].state;
+        e[i].ns = d[i].ns;
+        e[i].ncomp = d[i].prob.ncomp;
+        e[i].c_ns = d[i].prob.c_ns;
+        e[i].block_begin = blocks;
+        e[i].nblocks = static_cast<int>(
+            std::max<int64_t>(1, std::min<int64_t>(kMonitorBlocksPerDomain, (d[i].prob.N + 4095) / 4096)));
+        blocks += e[i].nblocks;
+    }
+    h->ndom = n;
+    h->total_blocks = blocks;
+    h->pad[0] = h->pad[1] = 0;
+    return blocks;
+}
+
+int monitor_encode(int storage, const MonitorDomain* d, int n, void* host)
+{
+    return storage == kF64 ? monitor_encode_t<double>(d, n, host) : monitor_encode_t<float>(d, n, host);
+}
+
+hipError_t launch_monitor(int storage, const void* table, int ndom, int total_blocks, double* partials, double* out,
+                          hipStream_t st)
+{
+    if (ndom < 1) return hipSuccess;
+    return by_storage(storage, [&](auto tag) {
+        using ST = decltype(tag);
+        hipLaunchKernelGGL((k_monitor<ST>), dim3(total_blocks), dim3(kRedThreads), 0, st,
+                           static_cast<const char*>(table), partials);
+        hipLaunchKernelGGL((k_monitor_reduce<ST>), dim3(ndom), dim3(kRedThreads), 0, st,
+                           static_cast<const char*>(table), partials, out);
+        return hipGetLastError();
+    });
+}
+
+// ---------------------------------------------------------------------------
 // Batched launches.
 
 template <typename T>

@@ -297,6 +297,47 @@ int lbm_create(const lbm_domain* dom, const float* n_s, const double* rho_init, 
     return LBM_OK;
 }
 
+}  // extern "C"
+
+// A context over caller buffers that already hold (or will receive) its
+// state: no device work, no synchronisation (the server initialises the
+// state itself, on its admission stream).
+int hm_rt::ctx_bind(const lbm_domain* dom, const lbm_params* prm, const lbm_device_buffers* bufs, hipStream_t stream,
+                    lbm_ctx** out)
+{
+    *out = nullptr;
+    int rc = validate(dom, prm);
+    if (rc) return rc;
+    if (!bufs || !bufs->f_a || !bufs->f_b || !bufs->n_s || !bufs->scratch) return LBM_EINVAL;
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    c->dom = *dom;
+    c->prm = *prm;
+    c->prob = make_problem(dom, prm);
+    lbm_required_bytes(dom, prm, &c->sizes);
+    c->sl = scratch_layout(c->prob.N, prm->ncomp);
+    c->stream = stream;
+    c->cur = 0;
+    c->t = 0;
+    c->owned = false;
+    c->buf[0] = bufs->f_a;
+    c->buf[1] = bufs->f_b;
+    c->ns = static_cast<float*>(bufs->n_s);
+    c->scratch = static_cast<char*>(bufs->scratch);
+    int cus = 0;
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_EDEVICE;
+    }
+    c->launch = choose_launch(c->prob, cus);
+    *out = c;
+    return LBM_OK;
+}
+
+extern "C" {
+
 int lbm_step(lbm_ctx* c, int64_t nsteps)
 {
     if (!c || nsteps < 0) return LBM_EINVAL;

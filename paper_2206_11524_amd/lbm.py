@@ -317,7 +317,8 @@ SERVE_POLICY = {"fair": 0, "shortest-first": 1}
 
 class Request(C.Structure):
     _fields_ = [("dom", Domain), ("n_s", C.c_void_p), ("rho_init", C.c_void_p), ("params", Params),
-                ("max_steps", C.c_int64), ("conv_tol", C.c_double), ("rho_out", C.c_void_p)]
+                ("max_steps", C.c_int64), ("conv_tol", C.c_double), ("conv_window", C.c_int32),
+                ("conv_noise", C.c_int32), ("rho_out", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -402,25 +403,27 @@ class Server:
         self._keep = {}
 
     def submit(self, shape, ns, rho_init, params: Params, max_steps: int, conv_tol: float = 0.0,
-               want_rho: bool = False) -> int:
+               want_rho: bool = False, conv_window: int = 0, conv_noise: bool = False) -> int:
         ns = np.ascontiguousarray(ns, dtype=np.float32)
         rho_init = np.ascontiguousarray(rho_init, dtype=np.float64)
         out = np.empty_like(rho_init) if want_rho else None
         rq = Request(Domain(*[int(v) for v in shape]), ns.ctypes.data, rho_init.ctypes.data, params,
-                     int(max_steps), float(conv_tol), out.ctypes.data if out is not None else None)
+                     int(max_steps), float(conv_tol), int(conv_window), int(bool(conv_noise)),
+                     out.ctypes.data if out is not None else None)
         t = C.c_uint64()
         _check(self.lib.lbm_batch_submit(self.s, C.byref(rq), C.byref(t)), "lbm_batch_submit")
         if out is not None:
             self._keep[t.value] = out
         return t.value
 
-    def submit_workload(self, w, max_steps, conv_tol=0.0, want_rho=False, rho_shift=None, rounding=None):
+    def submit_workload(self, w, max_steps, conv_tol=0.0, want_rho=False, rho_shift=None, rounding=None,
+                        conv_window=0, conv_noise=False):
         if rho_shift is None:
             rho_shift = default_shift(self.storage, w.ncomp, w.rho)
         p = make_params(ncomp=w.ncomp, c_ns=w.c_ns, tau=w.tau, G=w.G, G_ads=w.G_ads, F_ext=w.F_ext,
                         g_scale=w.g_scale, storage=self.storage, rho_shift=rho_shift, reservoirs=w.reservoirs,
                         rounding=rounding)
-        return self.submit(w.shape, w.ns, w.rho, p, max_steps, conv_tol, want_rho)
+        return self.submit(w.shape, w.ns, w.rho, p, max_steps, conv_tol, want_rho, conv_window, conv_noise)
 
     def poll(self, ticket):
         r = Result()

@@ -199,3 +199,65 @@ def test_server_shortest_first_keeps_results_and_order(run_cells):
     work = [w.ncells * n for w, n in zip(ws, steps)]
     done = [r["t_done"] for r in res]
     assert sorted(range(len(ws)), key=lambda k: done[k]) == sorted(range(len(ws)), key=lambda k: work[k])
+
+
+def test_server_windowed_convergence_under_stochastic_rounding():
+    """A Darcy flow through a porous domain (two non-interacting components,
+    force along z) in FP16 with stochastic rounding settles within a few
+    thousand steps, but its momentum keeps the rounding noise of the 16-bit
+    state: a tolerance of 1e-6 on consecutive samples never fires.  Averaged
+    over windows of 8 samples with the noise floor on, the test stops the
+    request once the window means agree within their standard error, and the
+    result is still the request run alone for the same number of steps."""
+    storage = "f16s"
+    w = inputs.porous_domain(24, 4200)
+    w.G, w.G_ads, w.F_ext = 0.0, (0.0, 0.0), (0.0, 0.0, 1e-5)
+    srv = lbm.Server(storage=storage, max_slots=4, steps_per_tick=25, max_cells=32 ** 3)
+    t_plain = srv.submit_workload(w, 3000, conv_tol=1e-6)
+    t_win = srv.submit_workload(w, 100000, conv_tol=1e-6, want_rho=True, conv_window=8, conv_noise=True)
+    rp, rw = srv.wait(t_plain, 120.0), srv.wait(t_win, 300.0)
+    srv.close()
+    assert rp["status"] == 0 and not rp["converged"] and rp["steps_done"] == 3000
+    assert rw["status"] == 0 and rw["converged"] and rw["steps_done"] < 100000
+    assert rw["steps_done"] % 25 == 0 and rw["steps_done"] >= 2 * 8 * 25
+    sim = lbm.from_workload(w, storage=storage)
+    sim.step(rw["steps_done"])
+    m = sim.moments()
+    sim.close()
+    assert np.array_equal(rw["rho"], m["rho"])
+
+
+def test_server_rejects_bad_convergence_settings():
+    srv = lbm.Server(storage="f32", max_slots=2, steps_per_tick=10, max_cells=16 ** 3)
+    w = inputs.porous_domain(16, 4300)
+    for kw in ({"conv_window": -1}, {"conv_window": 5000}):
+        with pytest.raises(lbm.LbmError) as e:
+            srv.submit_workload(w, 10, conv_tol=1e-3, **kw)
+        assert e.value.code == lbm.LBM_EINVAL
+    srv.close()
+
+
+def test_server_pool_reuses_memory_across_many_requests():
+    """Requests of varying sizes through a budget that holds only a few at a
+    time: every one completes with its exact step count, the pool never
+    exceeds the budget, and results equal contexts run alone."""
+    storage = "f32"
+    sizes = [20, 28, 16, 24, 28, 20, 16, 24, 28, 20]
+    one = max(2 * lbm.required_bytes((e, e, e), lbm.make_params(storage=storage)).pop_bytes + 4 * e ** 3
+              for e in sizes)
+    srv = lbm.Server(storage=storage, max_slots=8, steps_per_tick=10, max_cells=28 ** 3,
+                     hbm_budget_bytes=int(2.5 * one))
+    ws = [inputs.porous_domain(e, 4400 + k) for k, e in enumerate(sizes)]
+    steps = [30 + 10 * (k % 4) for k in range(len(ws))]
+    ts = [srv.submit_workload(w, s, want_rho=True) for w, s in zip(ws, steps)]
+    res = [srv.wait(t, 120.0) for t in ts]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(ws)
+    for w, n, r in zip(ws, steps, res):
+        assert r is not None and r["status"] == 0 and r["steps_done"] == n
+        sim = lbm.from_workload(w, storage=storage)
+        sim.step(n)
+        m = sim.moments()
+        sim.close()
+        assert np.array_equal(r["rho"], m["rho"])
