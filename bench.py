@@ -247,6 +247,19 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
             "depth_trace": {"columns": ["t_s", "queued", "resident"], "rows": trace}}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The FP64 CPU oracle on the same workload, timed on the host cores for a
     bounded number of whole-domain steps."""
@@ -268,7 +281,7 @@ def cpu_baseline(w, budget_s=20.0):
     dt = time.perf_counter() - t0
     return {"value": round(w.ncells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{steps} full time steps of the {w.shape[0]}x{w.shape[1]}x{w.shape[2]} workload, "
-                      f"FP64, {dt:.1f} s"}
+                      f"FP64, {dt:.1f} s", "cpu_model": cpu_model()}
 
 
 def cpu_baseline_single_thread(w, planes=16, budget_s=6.0):
@@ -296,7 +309,8 @@ def cpu_baseline_single_thread(w, planes=16, budget_s=6.0):
     dt = time.perf_counter() - t0
     cells = nx * ny * (z1 - z0)
     return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full time steps of a {nx}x{ny}x{z1 - z0} slab of the workload, FP64, {dt:.1f} s"}
+            "sample": f"{steps} full time steps of a {nx}x{ny}x{z1 - z0} slab of the workload, FP64, {dt:.1f} s",
+            "cpu_model": cpu_model()}
 
 
 def main():

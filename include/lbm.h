@@ -224,6 +224,29 @@ typedef struct {
 
 int lbm_fill_state_get(lbm_ctx* ctx, const lbm_fill_query* q, lbm_fill_state* out);
 
+/* Permeability of Eq. (Permeability) along axis (0: x, 1: y, 2: z) at the
+ * current time t (Sec. 3.1): k = nu <rho u> / F, with <rho u> the mean over
+ * all N cells of rho u_macro[axis] (Eq. HMCSC_u_macro, the momentum that
+ * lbm_totals sums), F = F_ext[axis] of the context's parameters and
+ * nu = (tau - 1/2)/3 the lattice viscosity.  k_comp[s] = nu <rho_s
+ * u_macro[axis]> / F is component s's share (the mixture velocity weighted by
+ * that component's density; k_comp[0] + k_comp[1] = k); its ratio to the
+ * value of a run saturated with component s is the relative permeability of
+ * Eq. (relativePermeability).  The run should be at steady state; k is
+ * whatever the current state gives.  FP64, deterministic (fixed-order
+ * reduction).  Synchronises.  LBM_EINVAL for NULL arguments, an axis outside
+ * 0..2, F_ext[axis] = 0, or two components with different tau (no single
+ * viscosity). */
+typedef struct {
+    double k;            /* nu <rho u> / F                              */
+    double k_comp[2];    /* nu <rho_s u> / F (k_comp[1] = 0 if ncomp 1) */
+    double momentum;     /* <rho u_macro[axis]>, mean over the cells    */
+    double nu;           /* (tau - 1/2)/3                               */
+    int64_t time;
+} lbm_permeability;
+
+int lbm_permeability_get(lbm_ctx* ctx, int32_t axis, lbm_permeability* out);
+
 /* Canonical populations (see above) of the current state into f [ncomp*19*N].
  * Reservoir cells hold their prescribed equilibrium.  Synchronises. */
 int lbm_get_populations(lbm_ctx* ctx, double* f);

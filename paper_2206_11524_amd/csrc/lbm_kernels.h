@@ -105,6 +105,12 @@ struct FillQuery {
 hipError_t launch_fill(const Problem& p, const FillQuery& q, const double* rho, const double* pr, const float* ns,
                        double* partials, double* out, hipStream_t st);
 
+// Eq. (Permeability) sums from the FP64 densities rho and velocity u (after
+// the force pass): out[3] = {sum rho_0 u[axis], sum rho_1 u[axis], sum rho
+// u[axis]}.  partials needs 3 * moments_max_blocks() doubles.
+hipError_t launch_flux(const Problem& p, int axis, const double* rho, const double* u, double* partials, double* out,
+                       hipStream_t st);
+
 // One domain of a batched launch (host description).
 struct BatchDomain {
     Problem prob;

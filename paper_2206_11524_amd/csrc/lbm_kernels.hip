@@ -2119,6 +2119,25 @@ __global__ __launch_bounds__(kRedThreads) void k_fill(int nx, int ny, int nz, in
     block_sum<6>(acc, partials + static_cast<size_t>(blockIdx.x) * 6);
 }
 
+// Permeability (Eq. Permeability) from the FP64 fields: per-block sums of
+// rho_s u_macro[axis] for each component (the component's share of the
+// mixture momentum, used for relative permeabilities) and of rho u_macro[axis].
+__global__ __launch_bounds__(kRedThreads) void k_flux(int64_t N, int ncomp, int axis, const double* __restrict__ rho,
+                                                      const double* __restrict__ u, double* __restrict__ partials)
+{
+    double acc[3] = {0, 0, 0};
+    CELL_LOOP(n, N)
+    {
+        const double ua = u[static_cast<size_t>(axis) * N + n];
+        const double r0 = rho[n];
+        const double r1 = ncomp == 2 ? rho[static_cast<size_t>(N) + n] : 0.0;
+        acc[0] += r0 * ua;
+        acc[1] += r1 * ua;
+        acc[2] += (r0 + r1) * ua;
+    }
+    block_sum<3>(acc, partials + static_cast<size_t>(blockIdx.x) * 3);
+}
+
 // Fixed-order sum of nblocks partials of K doubles each (one block): the
 // result does not depend on timing.
 template <int K>
@@ -2346,6 +2365,15 @@ hipError_t launch_fill(const Problem& p, const FillQuery& q, const double* rho, 
     hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kRedThreads), 0, st, p.nx, p.ny, p.nz, p.N, q, ns_field, rho, pr, ns,
                        partials);
     hipLaunchKernelGGL(k_reduce<6>, dim3(1), dim3(kRedThreads), 0, st, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux(const Problem& p, int axis, const double* rho, const double* u, double* partials, double* out,
+                       hipStream_t st)
+{
+    const int nb = diag_blocks(p.N);
+    hipLaunchKernelGGL(k_flux, dim3(nb), dim3(kRedThreads), 0, st, p.N, p.ncomp, axis, rho, u, partials);
+    hipLaunchKernelGGL(k_reduce<3>, dim3(1), dim3(kRedThreads), 0, st, partials, nb, out);
     return hipGetLastError();
 }
 

@@ -461,6 +461,31 @@ int lbm_fill_state_get(lbm_ctx* c, const lbm_fill_query* q, lbm_fill_state* out)
     return LBM_OK;
 }
 
+int lbm_permeability_get(lbm_ctx* c, int32_t axis, lbm_permeability* out)
+{
+    if (!c || !out || axis < 0 || axis > 2) return LBM_EINVAL;
+    const double F = c->prm.F_ext[axis];
+    if (F == 0.0 || (c->prm.ncomp == 2 && c->prm.tau[0] != c->prm.tau[1])) return LBM_EINVAL;
+    const int rc = compute_totals(c, true, true, nullptr);  // FP64 densities and u_macro into the scratch
+    if (rc) return rc;
+    double* part = reinterpret_cast<double*>(c->scratch + c->sl.partials);
+    double* tots = reinterpret_cast<double*>(c->scratch + c->sl.totals);
+    HIP_TRY(hm::launch_flux(c->prob, axis, reinterpret_cast<const double*>(c->scratch + c->sl.rho),
+                            reinterpret_cast<const double*>(c->scratch + c->sl.u), part, tots, c->stream));
+    double h[3];
+    HIP_TRY(hipMemcpyAsync(h, tots, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double N = static_cast<double>(c->prob.N);
+    const double nu = (c->prm.tau[0] - 0.5) / 3.0;
+    out->nu = nu;
+    out->momentum = h[2] / N;
+    out->k = nu * out->momentum / F;
+    out->k_comp[0] = nu * (h[0] / N) / F;
+    out->k_comp[1] = c->prm.ncomp == 2 ? nu * (h[1] / N) / F : 0.0;
+    out->time = c->t;
+    return LBM_OK;
+}
+
 int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
 
 int lbm_set_time(lbm_ctx* c, int64_t t)

@@ -151,7 +151,7 @@ def _sphere_pack(shape, g, target_solid, rmin, rmax, zlo=0, zhi=None, batch=64):
 
 def electrode(n=256, seed=2000, res_layers=16, solid_fraction=0.5, rmin=6.0, rmax=12.0,
               binder_frac=0.2, G=0.9, G_ads=(-0.3, 0.3), rho_main=1.0, rho_dis=0.03,
-              tau=1.0) -> Workload:
+              tau=1.0, membrane=0) -> Workload:
     """Synthetic electrode for the electrolyte-filling workload.
 
     * spheres (n_s = 1) of radius U[rmin, rmax] fill ``res_layers <= z < n-res_layers``
@@ -162,10 +162,14 @@ def electrode(n=256, seed=2000, res_layers=16, solid_fraction=0.5, rmin=6.0, rma
     * component A (wetting, index 0) fills the inlet reservoir z < res_layers,
       component B fills everything else; reservoirs hold (rho_main, rho_dis) at the
       inlet and (rho_dis, rho_main) at the outlet.
+    * membrane > 0: Sec. 4's semi-permeable membranes of that many layers next
+      to each reservoir, with one bounce-back field per component (c_ns = 2):
+      the inlet membrane blocks B (n_s,B = 1), the outlet membrane blocks A;
+      the structure then lies between the membranes.
     """
     g = rng(seed)
     shape = (n, n, n)
-    zlo, zhi = res_layers, n - res_layers
+    zlo, zhi = res_layers + membrane, n - res_layers - membrane
     solid = _sphere_pack(shape, g, solid_fraction, rmin, rmax, zlo, zhi)
     noise = _gaussian_smooth(g.standard_normal((n, n, n)), 3.0)
     pore = ~solid
@@ -175,17 +179,21 @@ def electrode(n=256, seed=2000, res_layers=16, solid_fraction=0.5, rmin=6.0, rma
     thr = np.quantile(vals, 1.0 - binder_frac)
     binder = pore & (noise >= thr)
     zscore = (noise - vals.mean()) / vals.std()
-    ns = np.zeros((1, n, n, n), np.float32)
-    ns[0][binder] = np.clip(0.5 + 0.15 * zscore[binder], 0.2, 0.8)
-    ns[0][solid] = 1.0
+    ns = np.zeros((2 if membrane else 1, n, n, n), np.float32)
+    for c in range(ns.shape[0]):
+        ns[c][binder] = np.clip(0.5 + 0.15 * zscore[binder], 0.2, 0.8)
+        ns[c][solid] = 1.0
+    if membrane:
+        ns[1, res_layers:zlo] = 1.0      # inlet membrane: A only
+        ns[0, zhi:n - res_layers] = 1.0  # outlet membrane: B only
     r = np.empty((2, n, n, n))
     r[0] = rho_dis
     r[1] = rho_main
     r[0, :zlo] = rho_main
     r[1, :zlo] = rho_dis
-    res = [(2, 0, zlo, (rho_main, rho_dis)), (2, zhi, n, (rho_dis, rho_main))]
+    res = [(2, 0, res_layers, (rho_main, rho_dis)), (2, n - res_layers, n, (rho_dis, rho_main))]
     return Workload(shape, ns, r, ncomp=2, tau=(tau, tau), G=G, G_ads=tuple(G_ads), g_scale=3.0,
-                    reservoirs=res, name=f"electrode{n}")
+                    reservoirs=res, name=f"electrode{n}" + (f"_m{membrane}" if membrane else ""))
 
 
 def filling_cell(nxy=48, nz=64, seed=2100, res_layers=4, membrane=2, solid_fraction=0.45, rmin=4.0, rmax=7.0,
@@ -267,6 +275,26 @@ def washburn_channel(G_ads, ns_medium, H=500, L=2, res_width=4, gap=8, rho_main=
     res = [(0, 0, res_width, (rho_main, rho_dis)), (0, H - res_width, H, (rho_dis, rho_main))]
     return Workload((H, L, 1), ns, r, ncomp=2, tau=(1.0, 1.0), G=1.75, G_ads=(-G_ads, G_ads), g_scale=1.0,
                     reservoirs=res, name=f"washburn{H}_{G_ads}_{ns_medium}")
+
+
+def buckley_leverett_channel(ns_medium, rho_main, rho_dis, H=100, L=5, res_width=4, force=1e-4,
+                             G=1.75) -> Workload:
+    """Waterflooding set-up of the Supporting Information (Buckley-Leverett),
+    one cell deep in z (the paper's 2-D set-up): a homogenized medium of
+    uniform n_s (both components) between a fluid-1 reservoir at
+    x < res_width and a fluid-2 reservoir at x >= H - res_width, fluid 2
+    everywhere else at the start, no adhesion, G_inter = G, tau = 1, a body
+    force along +x (inlet to outlet).  The reservoirs and the initial phases
+    hold (rho_main, rho_dis) and (rho_dis, rho_main): the caller chooses them
+    (the two fluids' coexistence densities keep the reservoirs in equilibrium
+    with the bulk phases)."""
+    ns = np.full((1, 1, L, H), ns_medium, np.float32)
+    r = np.empty((2, 1, L, H))
+    r[0], r[1] = rho_dis, rho_main
+    r[0, ..., :res_width], r[1, ..., :res_width] = rho_main, rho_dis
+    res = [(0, 0, res_width, (rho_main, rho_dis)), (0, H - res_width, H, (rho_dis, rho_main))]
+    return Workload((H, L, 1), ns, r, ncomp=2, tau=(1.0, 1.0), G=G, G_ads=(0.0, 0.0), g_scale=1.0,
+                    F_ext=(force, 0.0, 0.0), reservoirs=res, name=f"buckley_leverett_{ns_medium}")
 
 
 def obstacle_channel(ns1, L=300, H=50, radius=16.5, spacing=60, first=30.0, res_width=4, force=5e-5,

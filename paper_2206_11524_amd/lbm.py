@@ -65,6 +65,11 @@ class FillState(C.Structure):
                 ("saturation", C.c_double), ("pore_volume", C.c_double), ("time", C.c_int64)]
 
 
+class Permeability(C.Structure):
+    _fields_ = [("k", C.c_double), ("k_comp", C.c_double * 2), ("momentum", C.c_double), ("nu", C.c_double),
+                ("time", C.c_int64)]
+
+
 class Totals(C.Structure):
     _fields_ = [("mass", C.c_double * 2), ("momentum", C.c_double * 3), ("time", C.c_int64),
                 ("finite", C.c_int32), ("pad", C.c_int32)]
@@ -82,6 +87,7 @@ SIGNATURES = {
     "lbm_totals_get": (C.c_int, [C.c_void_p, C.POINTER(Totals)]),
     "lbm_totals_get_static": (C.c_int, [C.c_void_p, C.POINTER(Totals)]),
     "lbm_fill_state_get": (C.c_int, [C.c_void_p, C.POINTER(FillQuery), C.POINTER(FillState)]),
+    "lbm_permeability_get": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Permeability)]),
     "lbm_get_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_set_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_set_reservoir": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
@@ -260,6 +266,14 @@ class Simulation:
         _check(self.lib.lbm_fill_state_get(self.ctx, C.byref(q), C.byref(out)), "lbm_fill_state_get")
         return {"dp": out.dp, "p_inlet": out.p_inlet, "p_outlet": out.p_outlet, "saturation": out.saturation,
                 "pore_volume": out.pore_volume, "time": out.time}
+
+    def permeability(self, axis=0):
+        """Permeability of Eq. (Permeability) along ``axis`` with each
+        component's share (see ``lbm_permeability_get``)."""
+        out = Permeability()
+        _check(self.lib.lbm_permeability_get(self.ctx, axis, C.byref(out)), "lbm_permeability_get")
+        return {"k": out.k, "k_comp": (out.k_comp[0], out.k_comp[1]), "momentum": out.momentum, "nu": out.nu,
+                "time": out.time}
 
     def populations(self) -> np.ndarray:
         nx, ny, nz = self.shape

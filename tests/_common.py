@@ -33,6 +33,24 @@ def front_position(rho, x0, tail=5):
     return i + phi[i] / (phi[i] - phi[i + 1]) - x0
 
 
+def washburn_contact_angle(rate, B, gamma=0.077, eta=1.0 / 6.0):
+    """Contact angle (degrees) behind a Washburn rate (Eq. Washburn): the fit
+    x_inter^2 = rate * t gives A^2 = rate / B at a given B, and A^2 = gamma
+    cos(theta) / (2 eta), so cos(theta) = 2 eta rate / (B gamma).  gamma is
+    the interfacial tension of the Table 1 fluids at G_inter = 1.75 (the
+    large-domain value of Sec. 3.3), eta = rho nu with tau = 1 and the
+    nominal density 1 (the pair that turns Table 3's A column into its theta
+    column, gamma / (2 eta) = 0.231).  Returns 0
+    where the rate exceeds what complete wetting allows (cos > 1)."""
+    c = 2.0 * eta * rate / (B * gamma)
+    return float(np.degrees(np.arccos(min(c, 1.0))))
+
+
+def huang_contact_angle(G_ads, G_inter=1.75, rho_1=0.99, rho_dis=0.01):
+    """theta_H of Eq. (contactAngle), degrees: cos = 4 G_ads / (G_inter (rho_1 - rho_dis))."""
+    return float(np.degrees(np.arccos(4.0 * G_ads / (G_inter * (rho_1 - rho_dis)))))
+
+
 def build_c_driver(out):
     """Compile tests/c_driver/abi_driver.c against include/lbm.h and link it to
     the built library (gcc only; no Python or PyTorch in the program)."""

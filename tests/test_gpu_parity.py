@@ -377,3 +377,52 @@ def test_fill_state_matches_definitions_on_oracle_fields():
         assert abs(st["saturation"] - sat) < 1e-12 and abs(st["pore_volume"] / wfl.sum() - 1) < 1e-12
         assert st["time"] == 40
     sim.close()
+
+
+def test_permeability_matches_definition_on_oracle_fields():
+    """lbm_permeability_get (Eq. Permeability) on a two-component domain with
+    a heterogeneous n_s, adhesion and a body force along x and y, FP64, after
+    60 steps: k and each component's share against nu sum rho_s u / (N F) on
+    the oracle's fields, 1e-10 relative."""
+    rng = np.random.default_rng(77)
+    w = inputs.uniform((11, 9, 6), 0.0, rho=(0.6, 0.4))
+    w.ns[:] = rng.uniform(0.0, 0.6, w.ns.shape).astype(np.float32)
+    w.rho[0] += rng.uniform(-0.05, 0.05, w.rho[0].shape)
+    w.G, w.G_ads, w.g_scale, w.tau, w.F_ext = 0.9, (-0.1, 0.1), 3.0, (0.9, 0.9), (2e-5, -1e-5, 0.0)
+    o = oracle_for(w)
+    mo = o.moments(o.run(o.init(w.rho), 60))
+    sim = lbm.from_workload(w, storage="f64")
+    sim.step(60)
+    nu, N = 0.4 / 3, w.ncells
+    for axis in (0, 1):
+        got = sim.permeability(axis)
+        F = w.F_ext[axis]
+        ref = [nu * (mo["rho"][s] * mo["u"][axis]).sum() / (N * F) for s in range(2)]
+        assert abs(got["nu"] - nu) < 1e-15 and got["time"] == 60
+        for a, b in zip(got["k_comp"], ref):
+            assert abs(a - b) <= 1e-10 * abs(b), (axis, a, b)
+        assert abs(got["k"] - sum(ref)) <= 1e-10 * abs(sum(ref))
+    with pytest.raises(RuntimeError):
+        sim.permeability(2)  # no force along z
+    sim.close()
+
+
+@pytest.mark.parametrize("ns_value", [0.01, 0.1, 0.5, 0.9, 0.999])
+def test_permeability_of_a_uniform_medium_is_gs_perm(ns_value):
+    """Sec. 3.1's single-phase case in 3-D: a fully periodic medium of uniform
+    n_s under a body force reaches k = (1 - n_s) nu / (2 n_s) (Eq. GS_perm) at
+    steady state; the momentum approaches it as 1 - (1 - 2 n_s)^t, so 20000
+    steps leave nothing measurable (0.998^20000 = 4e-18 at n_s = 0.999).
+    FP64 library output, 1e-10 relative plus 1e-12 absolute: at n_s = 0.999
+    the mean momentum (5e-9) is a sum of populations near 0.05 whose FP64
+    rounding (1e-17 each) is a few 1e-10 of it."""
+    w = inputs.uniform((6, 5, 4), ns_value, rho=(1.0,), ncomp=1)
+    w.tau, w.F_ext = (0.8, 0.8), (1e-5, 0.0, 0.0)
+    sim = lbm.from_workload(w, storage="f64")
+    sim.step(20000)
+    got = sim.permeability(0)
+    sim.close()
+    nu = 0.3 / 3
+    want = (1 - float(np.float32(ns_value))) * nu / (2 * float(np.float32(ns_value)))
+    assert abs(got["k"] - want) <= 1e-10 * want + 1e-12, (got, want)
+    assert got["k_comp"][1] == 0.0 and got["k_comp"][0] == got["k"]

@@ -77,6 +77,18 @@ MUTANTS = [
 ]
 
 
+# Pins too slow to run against every mutant, each with a mutant it must catch:
+# (name, text, replacement, occurrence, pin)
+TARGETED = [
+    ("macroscopic velocity not weighted by 1 - n_s, against the Buckley-Leverett pin",
+     "m += (1.0 - ns_at(p, ns, s, n)) * (js", "m += (js", 1,
+     "test_oracle_buckley_leverett.py::test_front_moves_with_the_buckley_leverett_shock"),
+    ("adhesion halved, against the stored Washburn fronts behind the contact-angle pin",
+     "Fads[a] = -rho_s[s] * p->G_ads[s] * g[a];", "Fads[a] = -0.5 * rho_s[s] * p->G_ads[s] * g[a];", 1,
+     "test_oracle_washburn.py::test_stored_full_size_front_is_the_oracles"),
+]
+
+
 def _mutate(src: str, old: str, new: str, k: int) -> str:
     pos = -1
     for _ in range(k):
@@ -85,10 +97,10 @@ def _mutate(src: str, old: str, new: str, k: int) -> str:
     return src[:pos] + new + src[pos + len(old):]
 
 
-def _run_pins(lib: str) -> subprocess.CompletedProcess:
+def _run_pins(lib: str, pins=None) -> subprocess.CompletedProcess:
     env = dict(os.environ, HMCSC_ORACLE_LIB=lib)
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
-           *[os.path.join(TESTS, f) for f in PINS]]
+           *[os.path.join(TESTS, f) for f in (pins or PINS)]]
     return subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
 
 
@@ -106,3 +118,14 @@ def test_mutant_fails_a_pin(tmp_path, name, old, new, k):
     lib = ref.compile_to(str(msrc), str(tmp_path / "mutant.so"))
     r = _run_pins(lib)
     assert r.returncode != 0, f"no pin caught the mutant '{name}'"
+
+
+@pytest.mark.parametrize("name,old,new,k,pin", TARGETED, ids=[m[0] for m in TARGETED])
+def test_targeted_mutant_fails_its_pin(tmp_path, name, old, new, k, pin):
+    src = open(ref.SRC).read()
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(_mutate(src, old, new, k))
+    lib = ref.compile_to(str(msrc), str(tmp_path / "mutant.so"))
+    assert _run_pins(ref.compile_to(ref.SRC, str(tmp_path / "orig.so")), [pin]).returncode == 0, pin
+    r = _run_pins(lib, [pin])
+    assert r.returncode != 0, f"the pin {pin} did not catch the mutant '{name}'"

@@ -27,7 +27,7 @@ import pytest
 from oracle.ref import Oracle, Reservoir, Setup
 from paper_2206_11524_amd import inputs
 
-from _common import front_position
+from _common import front_position, huang_contact_angle, washburn_contact_angle
 
 XM = 12  # first cell of the gray medium
 
@@ -95,3 +95,61 @@ def test_stored_full_size_front_is_the_oracles():
         t = int(tr)
         x = front_position(o.moments(f)["rho"], 12)
         assert x is not None and abs(x - xr) < 1e-9, (t, x, xr)
+
+
+def _table3_rows():
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table3_washburn.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                b, g, ns, A, B, _ = line.split()
+                rows.append((b, float(g), float(ns), float(A), float(B)))
+    return rows
+
+
+def test_contact_angle_conversion_reproduces_table3():
+    """The conversion of a Washburn fit to a contact angle, and Eq.
+    (contactAngle), against Table 3's own columns: theta from each printed A
+    at the printed B (cos theta = 2 eta A^2 / gamma) lands within 1 degree of
+    the printed theta, and theta_H of Eq. (contactAngle) within 0.1 degree of
+    the printed theta_H (values of Sec. 3.4's table, not in the fixture)."""
+    theta = [70.8, 67.7, 64.1, 59.2, 52.9, 45.9, 36.0, 21.4]
+    theta_h = [83.3, 76.5, 69.5, 62.2, 54.3, 45.6, 35.3, 21.1]
+    rows = [r for r in _table3_rows() if r[0] == "A"]
+    for (b, g, ns, A, B), th, thh in zip(rows, theta, theta_h):
+        assert abs(washburn_contact_angle(A * A * B, B) - th) < 1.0, (g, washburn_contact_angle(A * A * B, B), th)
+        assert abs(huang_contact_angle(g) - thh) < 0.1, (g, huang_contact_angle(g), thh)
+
+
+def _stored_rates():
+    d = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "washburn_front_oracle.txt"), comments="#")
+    out = {}
+    for g, ns in sorted({(round(a, 2), round(b, 1)) for a, b in d[:, :2]}):
+        sel = (np.round(d[:, 0], 2) == g) & (np.round(d[:, 1], 1) == ns) & ~np.isnan(d[:, 3])
+        out[(g, ns)] = np.polyfit(d[sel, 2], d[sel, 3] ** 2, 1)[0]
+    return out
+
+
+def test_contact_angle_from_washburn_rates_follows_huang():
+    """Eq. (contactAngle) as Table 3 tests it: the contact angle behind the
+    oracle's Washburn rates at the paper's size (H = 500, t <= 5e4; the stored
+    fronts, which the current oracle reproduces, see above), taken at the
+    fixed B = 0.0481 of Table 3's left block, against Huang's theta_H.
+
+    * Within 10 degrees of theta_H for G_ads <= 0.25 (theta_H 83 .. 54
+      degrees); measured 1.5 .. 5.6 degrees below it, where the paper's own
+      fits sit 1.4 .. 12.5 degrees below.
+    * theta falls strictly as G_ads rises over all eight rows.
+    * For G_ads >= 0.3 the rate grows faster than cos(theta_H): theta lies 11
+      .. 23 degrees below theta_H and the G_ads = 0.4 rate exceeds what
+      complete wetting allows at this B (reported, not asserted)."""
+    rates = _stored_rates()
+    ga = [0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4]
+    th = [washburn_contact_angle(rates[(g, 0.5)], 0.0481) for g in ga]
+    thh = [huang_contact_angle(g) for g in ga]
+    print("theta", np.round(th, 1), "theta_H", np.round(thh, 1))
+    for g, a, b in zip(ga, th, thh):
+        if g <= 0.25:
+            assert abs(a - b) < 10.0, (g, a, b)
+    cos = [2 * (1 / 6) * rates[(g, 0.5)] / (0.0481 * 0.077) for g in ga]
+    assert np.all(np.diff(cos) > 0), cos
