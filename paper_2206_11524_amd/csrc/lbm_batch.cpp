@@ -57,7 +57,7 @@ class BatchRunner {
         // whole share late
         grid_ = std::max(8, cus * hm::batch_blocks_per_cu(storage, ncomp, c_ns, tile_x, tile_y));
         cus_ = std::max(cus, 1);
-        tpc_ = std::max(1, hm_rt::env_int("LBM_BATCH_TILES_PER_CU", 2));
+        tpc_ = std::max(0, hm_rt::env_int("LBM_BATCH_TILES_PER_CU", 0));  // 0: planned per launch
         maxc_ = std::max(4, hm_rt::env_int("LBM_BATCH_MAX_CHUNK", 64));
         for (int j = 0; j < 2; ++j) {
             if (hipMalloc(&dev_[j], bytes_) != hipSuccess) return LBM_ENOMEM;
@@ -101,13 +101,11 @@ class BatchRunner {
         const int j = slot_;
         slot_ ^= 1;
         HIP_TRY(hipEventSynchronize(copied_[j]));  // host copy j is free again
-        // z-chunks from the batch as a whole: about tpc_ tiles per CU, none
-        // longer than maxc_ planes (blocks stride over tiles of unequal
-        // domains, shorter tiles balance them; longer tiles pay the pipeline
-        // fill of a tile less often), none shorter than 16 (each chunk
-        // re-reads two halo planes) unless the batch would then give fewer
-        // than two tiles per CU: a few small domains alone would leave most
-        // of the GPU idle, and the halo re-reads cost little there
+        // z-chunks from the batch as a whole, none longer than maxc_ planes,
+        // none shorter than 16 (each chunk re-reads two halo planes) unless
+        // the batch would then give fewer than two tiles per CU (a few small
+        // domains alone would leave most of the GPU idle, and the halo
+        // re-reads cost little there)
         balanced_.assign(d, d + n);
         int64_t cols = 0, tiles16 = 0;
         for (const hm::BatchDomain& b : balanced_) {
@@ -116,13 +114,19 @@ class BatchRunner {
             tiles16 += c * ((b.prob.nz + 15) / 16);
         }
         const int64_t min_chunk = tiles16 >= 2 * static_cast<int64_t>(cus_) ? 16 : 4;
-        const int64_t per_cols =
-            std::max<int64_t>(1, (tpc_ * static_cast<int64_t>(cus_) + cols - 1) / std::max<int64_t>(cols, 1));
-        for (hm::BatchDomain& b : balanced_) {
+        auto chunk_of = [&](const hm::BatchDomain& b, int64_t per_cols) {
             const int64_t chunks = std::max<int64_t>(per_cols, (b.prob.nz + maxc_ - 1) / maxc_);
-            b.zchunk = static_cast<int>(
+            return static_cast<int>(
                 std::min<int64_t>(b.prob.nz, std::max<int64_t>(min_chunk, (b.prob.nz + chunks - 1) / chunks)));
+        };
+        int64_t per_cols = 1;
+        if (tpc_ > 0) {
+            // fixed aim of tpc_ tiles per CU (LBM_BATCH_TILES_PER_CU)
+            per_cols = std::max<int64_t>(1, (tpc_ * static_cast<int64_t>(cus_) + cols - 1) / std::max<int64_t>(cols, 1));
+        } else {
+            per_cols = plan_chunks(chunk_of, min_chunk);
         }
+        for (hm::BatchDomain& b : balanced_) b.zchunk = chunk_of(b, per_cols);
         // longest tiles first: blocks take tiles in table order, so the
         // short ones fill in at the end (longest-processing-time order)
         std::stable_sort(balanced_.begin(), balanced_.end(), [](const hm::BatchDomain& a, const hm::BatchDomain& b) {
@@ -174,8 +178,74 @@ class BatchRunner {
     }
 
   private:
+    // Chunks per tile column shared by the domains of balanced_ (each capped
+    // by chunk_of).  Blocks take tiles w, w + G, w + 2G, ... of the table
+    // (G = grid_, tiles ordered longest first, each domain's tiles chunk by
+    // chunk), so a launch lasts about as long as the most loaded of the G
+    // block classes.  Each candidate is priced by that load in planes, a
+    // tile adding kTileCost planes for its two halo planes and its pipeline
+    // fill; the cheapest wins, ties going to fewer tiles.  The choice
+    // depends only on the domains' shapes and is kept until they change.
+    template <typename ChunkOf>
+    int64_t plan_chunks(ChunkOf chunk_of, int64_t min_chunk)
+    {
+        constexpr int64_t kTileCost = 3;
+        shapes_now_.clear();
+        for (const hm::BatchDomain& b : balanced_) {
+            shapes_now_.push_back(b.prob.nx);
+            shapes_now_.push_back(b.prob.ny);
+            shapes_now_.push_back(b.prob.nz);
+        }
+        shapes_now_.push_back(static_cast<int>(min_chunk));
+        if (shapes_now_ == shapes_planned_) return planned_;
+        int64_t cmax = 1;
+        for (const hm::BatchDomain& b : balanced_)
+            cmax = std::max<int64_t>(cmax, (b.prob.nz + min_chunk - 1) / min_chunk);
+        cmax = std::min<int64_t>(cmax, 256);
+        std::vector<int64_t> load(static_cast<size_t>(std::max(grid_, 1)));
+        std::vector<std::pair<int, int64_t>> order;  // (zchunk, domain index)
+        int64_t best = 1, best_cost = -1, best_tiles = 0;
+        std::vector<int> zcs, prev_zcs;
+        for (int64_t c = 1; c <= cmax; ++c) {
+            order.clear();
+            zcs.clear();
+            for (size_t i = 0; i < balanced_.size(); ++i) {
+                const int zc = chunk_of(balanced_[i], c);
+                order.emplace_back(zc, static_cast<int64_t>(i));
+                zcs.push_back(zc);
+            }
+            if (zcs == prev_zcs) continue;  // same chunking as the previous candidate
+            prev_zcs = zcs;
+            std::stable_sort(order.begin(), order.end(),
+                             [](const std::pair<int, int64_t>& a, const std::pair<int, int64_t>& b) {
+                                 return a.first > b.first;
+                             });
+            std::fill(load.begin(), load.end(), 0);
+            int64_t w = 0;
+            for (const auto& o : order) {
+                const hm::BatchDomain& b = balanced_[static_cast<size_t>(o.second)];
+                const int64_t tcols = static_cast<int64_t>((b.prob.nx + tx_ - 1) / tx_) * ((b.prob.ny + ty_ - 1) / ty_);
+                for (int64_t z0 = 0; z0 < b.prob.nz; z0 += o.first) {
+                    const int64_t len = std::min<int64_t>(o.first, b.prob.nz - z0) + kTileCost;
+                    for (int64_t t = 0; t < tcols; ++t, ++w) load[static_cast<size_t>(w % grid_)] += len;
+                }
+            }
+            const int64_t cost = *std::max_element(load.begin(), load.end());
+            if (best_cost < 0 || cost < best_cost || (cost == best_cost && w < best_tiles)) {
+                best = c;
+                best_cost = cost;
+                best_tiles = w;
+            }
+        }
+        shapes_planned_ = shapes_now_;
+        planned_ = best;
+        return best;
+    }
+
     int storage_ = 0, ncomp_ = 0, c_ns_ = 0, tx_ = 64, ty_ = 8, kmax_ = 1, grid_ = 512, cus_ = 256;
-    int tpc_ = 2, maxc_ = 64;  // tiles per CU aimed at, longest z-chunk
+    int tpc_ = 0, maxc_ = 64;  // tiles per CU aimed at (0: planned), longest z-chunk
+    std::vector<int> shapes_now_, shapes_planned_;
+    int64_t planned_ = 1;
     std::vector<hm::BatchDomain> balanced_;
     size_t bytes_ = 0;
     hipStream_t stream_ = nullptr;
