@@ -97,35 +97,62 @@ def _mutate(src: str, old: str, new: str, k: int) -> str:
     return src[:pos] + new + src[pos + len(old):]
 
 
-def _run_pins(lib: str, pins=None) -> subprocess.CompletedProcess:
+def _run_pins(lib: str, pins=None, threads=None) -> subprocess.CompletedProcess:
     env = dict(os.environ, HMCSC_ORACLE_LIB=lib)
+    if threads:
+        env["OMP_NUM_THREADS"] = str(threads)
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
            *[os.path.join(TESTS, f) for f in (pins or PINS)]]
-    return subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
 
 
-def test_unmodified_oracle_passes_the_pins(tmp_path):
-    lib = ref.compile_to(ref.SRC, str(tmp_path / "orig.so"))
-    r = _run_pins(lib)
-    assert r.returncode == 0, r.stdout[-2000:]
+# The mutants are independent: they are compiled and checked four at a time
+# (two OpenMP threads each, so the host is not oversubscribed), once per
+# session, and each parametrized test reads its own outcome.
+WORKERS, THREADS = 4, 2
 
 
-@pytest.mark.parametrize("name,old,new,k", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_mutant_fails_a_pin(tmp_path, name, old, new, k):
+def _check(tmp, key, old, new, k, pins):
     src = open(ref.SRC).read()
-    msrc = tmp_path / "mutant.c"
-    msrc.write_text(_mutate(src, old, new, k))
-    lib = ref.compile_to(str(msrc), str(tmp_path / "mutant.so"))
-    r = _run_pins(lib)
-    assert r.returncode != 0, f"no pin caught the mutant '{name}'"
+    tag = "".join(ch if ch.isalnum() else "_" for ch in key)[:60]
+    msrc = os.path.join(tmp, f"{tag}.c")
+    with open(msrc, "w") as fh:
+        fh.write(_mutate(src, old, new, k) if old is not None else src)
+    lib = ref.compile_to(msrc, os.path.join(tmp, f"{tag}.so"))
+    r = _run_pins(lib, pins, THREADS)
+    return r.returncode, r.stdout[-2000:]
 
 
-@pytest.mark.parametrize("name,old,new,k,pin", TARGETED, ids=[m[0] for m in TARGETED])
-def test_targeted_mutant_fails_its_pin(tmp_path, name, old, new, k, pin):
-    src = open(ref.SRC).read()
-    msrc = tmp_path / "mutant.c"
-    msrc.write_text(_mutate(src, old, new, k))
-    lib = ref.compile_to(str(msrc), str(tmp_path / "mutant.so"))
-    assert _run_pins(ref.compile_to(ref.SRC, str(tmp_path / "orig.so")), [pin]).returncode == 0, pin
-    r = _run_pins(lib, [pin])
-    assert r.returncode != 0, f"the pin {pin} did not catch the mutant '{name}'"
+@pytest.fixture(scope="module")
+def outcomes(tmp_path_factory):
+    from concurrent.futures import ThreadPoolExecutor
+    tmp = str(tmp_path_factory.mktemp("mutants"))
+    jobs = {("pins", "unmodified"): (None, None, 0, None)}
+    for name, old, new, k in MUTANTS:
+        jobs[("pins", name)] = (old, new, k, None)
+    for name, old, new, k, pin in TARGETED:
+        jobs[("targeted", name)] = (old, new, k, [pin])
+        jobs[("targeted-unmodified", name)] = (None, None, 0, [pin])
+    with ThreadPoolExecutor(WORKERS) as pool:
+        futs = {key: pool.submit(_check, tmp, key[0] + key[1], *job) for key, job in jobs.items()}
+        return {key: f.result() for key, f in futs.items()}
+
+
+def test_unmodified_oracle_passes_the_pins(outcomes):
+    rc, out = outcomes[("pins", "unmodified")]
+    assert rc == 0, out
+
+
+@pytest.mark.parametrize("name", [m[0] for m in MUTANTS])
+def test_mutant_fails_a_pin(outcomes, name):
+    rc, _ = outcomes[("pins", name)]
+    assert rc != 0, f"no pin caught the mutant '{name}'"
+
+
+@pytest.mark.parametrize("name", [m[0] for m in TARGETED])
+def test_targeted_mutant_fails_its_pin(outcomes, name):
+    pin = [m[4] for m in TARGETED if m[0] == name][0]
+    rc0, out0 = outcomes[("targeted-unmodified", name)]
+    assert rc0 == 0, (pin, out0)
+    rc, _ = outcomes[("targeted", name)]
+    assert rc != 0, f"the pin {pin} did not catch the mutant '{name}'"
