@@ -163,14 +163,16 @@ def ensemble(storage="f16s", ndom=64, steps=100, warmup=10, seed=3000):
 
 
 def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=100, drain_s=120.0, tile_x=0,
-            policy="fair", run_cells=0, conv_window=8):
+            policy="fair", run_cells=0, conv_window=8, compare_group=False):
     """Continuous-batching serving: Poisson arrivals at `rate` per second for
     `seconds`, each a porous domain of edge U{48..192} asking for U{2000..20000}
     steps or convergence to 1e-6 relative change of its momentum, tested on
     window means of `conv_window` samples (one per tick) with the noise floor
     of the stochastically rounded state; reports completion latency
     percentiles and the aggregate MLUPS of the server under the given sharing
-    policy ("fair" or "shortest-first")."""
+    policy ("fair" or "shortest-first").  With compare_group the same domains
+    are afterwards stepped together as one group (all resident, one batched
+    launch per step): the batched rate of that same mix, beside the server's."""
     from paper_2206_11524_amd import inputs, lbm
 
     g = np.random.Generator(np.random.PCG64(seed))
@@ -231,6 +233,22 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
             last = time.perf_counter()
     st = srv.stats()
     srv.close()
+    same_mix = None
+    if compare_group:
+        # the same domains, all resident, stepped together by one batched launch per step
+        sims = [lbm.from_workload(w, storage=storage) for w, _ in reqs]
+        grp = lbm.Group(sims)
+        grp.step(10)
+        sims[0].sync()
+        tg = time.perf_counter()
+        grp.step(50)
+        sims[0].sync()
+        tg = time.perf_counter() - tg
+        same_mix = round(sum(w.ncells for w, _ in reqs) * 50 / tg / 1e6, 1)
+        grp.close()
+        for sim in sims:
+            sim.close()
+        del sims
     done = [r for r in res if r is not None and r["status"] == 0]
     lat = np.array([r["t_done"] - r["t_submit"] for r in done])
     steps_asked = {k: s for k, (_, s) in enumerate(reqs)}
@@ -244,6 +262,7 @@ def serving(rate=0.5, seconds=30.0, storage="f16s", seed=4000, steps_per_tick=10
             "p99_latency_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
             "aggregate_mlups": round(st["cell_updates"] / max(st["busy_seconds"], 1e-9) / 1e6, 1),
             "max_in_system": depth, "ticks": st["ticks"],
+            **({"grouped_same_mix_mlups": same_mix} if same_mix is not None else {}),
             "depth_trace": {"columns": ["t_s", "queued", "resident"], "rows": trace}}
 
 
@@ -403,7 +422,7 @@ def main():
     if args.serve_burst > 0:
         line["serving_saturated"] = serving(float(args.serve_burst), 1.0, drain_s=args.serve_drain,
                                             tile_x=args.serve_tile, policy=args.serve_policy,
-                                            run_cells=args.serve_run_cells, seed=4500)
+                                            run_cells=args.serve_run_cells, seed=4500, compare_group=True)
         print(f"# serving (saturated): {line['serving_saturated']}", file=sys.stderr, flush=True)
     if args.serve_rate > 0:
         line["serving"] = serving(args.serve_rate, args.serve_seconds, drain_s=args.serve_drain,
