@@ -120,17 +120,18 @@ struct F16 : Half16 {
     {
         return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v * scale));
     }
-    // Stochastic rounding with 16 random bits r16 (v_cvt_sr_f16_f32): the
+    // Stochastic rounding with the random word r (v_cvt_sr_f16_f32): the
     // instruction reads its random operand as a binary fraction from the top
     // bit down and rounds the magnitude up with probability equal to the
     // value's fraction of the binary16 spacing, subnormals included (checked
     // on the device: up only for bit 31 at half a spacing, frequencies equal
-    // to the fraction, exact values unchanged, inf and NaN kept).  r16 goes to
-    // the top half, so the probability is resolved to 2^-16.
-    static __device__ __forceinline__ E enc_sr(T v, T scale, uint32_t r16)
+    // to the fraction, exact values unchanged, inf and NaN kept).  The top 16
+    // bits of r are random (see lcg24), so the probability is resolved to
+    // 2^-16.
+    static __device__ __forceinline__ E enc_sr(T v, T scale, uint32_t r)
     {
         half2_t h = {0, 0};
-        h = __builtin_amdgcn_cvt_sr_f16_f32(h, v * scale, r16 << 16, false);
+        h = __builtin_amdgcn_cvt_sr_f16_f32(h, v * scale, r, false);
         return __builtin_bit_cast(uint16_t, h[0]);
     }
 };
@@ -146,12 +147,12 @@ struct BF16 : Half16 {
     {
         return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v * scale));
     }
-    // Stochastic rounding with 16 random bits (v_cvt_sr_bf16_f32, the same
+    // Stochastic rounding with the random word r (v_cvt_sr_bf16_f32, the same
     // convention as the binary16 instruction).
-    static __device__ __forceinline__ E enc_sr(T v, T scale, uint32_t r16)
+    static __device__ __forceinline__ E enc_sr(T v, T scale, uint32_t r)
     {
         bf162_t h = {0, 0};
-        h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v * scale, r16 << 16, false);
+        h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v * scale, r, false);
         return __builtin_bit_cast(uint16_t, h[0]);
     }
 };
@@ -170,15 +171,15 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
 }
 constexpr uint32_t kGolden = 0x9e3779b9u;
 
-// Marsaglia's xorshift32 step (shifts 13, 17, 5): the following random words
-// of one cell, after fmix32 has seeded them.
-__device__ __forceinline__ uint32_t xorshift32(uint32_t x)
-{
-    x ^= x << 13;
-    x ^= x >> 17;
-    x ^= x << 5;
-    return x;
-}
+// The following random words of one (cell, component), after fmix32 has
+// seeded them: a linear congruential step modulo 2^24 (multiplier = 1 mod 4,
+// odd increment: full period by Hull and Dobell's conditions) on the low 24
+// bits of the previous word, kept as the 32-bit value a*x + c, whose top 16
+// bits the rounding reads.  One 24-bit multiply-add (v_mad_u32_u24) per
+// stored value.
+constexpr uint32_t kLcgA = 0x6d2b79u, kLcgC = 0x2b5a3fu;
+static_assert(kLcgA % 4 == 1 && kLcgC % 2 == 1 && kLcgA < (1u << 24), "full-period LCG modulo 2^24");
+__device__ __forceinline__ uint32_t lcg24(uint32_t x) { return (x & 0xffffffu) * kLcgA + kLcgC; }
 
 // Two 16-bit values of one (cell, direction) in one 32-bit word of the pair
 // layout: component 0 in the low half, component 1 in the high half.  The
@@ -200,18 +201,18 @@ struct PairCodec {
         }
     }
     // stochastic rounding (see F16::enc_sr) of a into the low and b into the
-    // high half of one word
+    // high half of one word, with the random words ra and rb
     static __device__ __forceinline__ uint32_t enc_sr(float a, float b, uint32_t ra, uint32_t rb)
     {
         if constexpr (std::is_same_v<ST, BF16>) {
             bf162_t h = {0, 0};
-            h = __builtin_amdgcn_cvt_sr_bf16_f32(h, a, ra << 16, false);
-            h = __builtin_amdgcn_cvt_sr_bf16_f32(h, b, rb << 16, true);
+            h = __builtin_amdgcn_cvt_sr_bf16_f32(h, a, ra, false);
+            h = __builtin_amdgcn_cvt_sr_bf16_f32(h, b, rb, true);
             return __builtin_bit_cast(uint32_t, h);
         } else {
             half2_t h = {0, 0};
-            h = __builtin_amdgcn_cvt_sr_f16_f32(h, a, ra << 16, false);
-            h = __builtin_amdgcn_cvt_sr_f16_f32(h, b, rb << 16, true);
+            h = __builtin_amdgcn_cvt_sr_f16_f32(h, a, ra, false);
+            h = __builtin_amdgcn_cvt_sr_f16_f32(h, b, rb, true);
             return __builtin_bit_cast(uint32_t, h);
         }
     }
@@ -959,19 +960,20 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
             else relax_dir(k, i, h[i], h[i + 9], pi, po);
         };
         if (a.sr) {
-            // counter: (cell, component) mixed with the time step, then the direction
-            // 32 random bits per direction pair (i, i+9), 16 for each value:
-            // fmix32 of (cell, component, time), then xorshift32 steps
+            // one random word per stored value: fmix32 of (cell, component,
+            // time step) for the rest population, then lcg24 steps in the
+            // order of the stores
             const uint32_t cell = static_cast<uint32_t>(z) * static_cast<uint32_t>(plane) + static_cast<uint32_t>(y * a.nx + x);
-            uint32_t r = fmix32(t_key ^ (2u * cell + static_cast<uint32_t>(s))) | 1u;  // nonzero state
-            ST::bst(ST::enc_sr(rest(), a.scale, r >> 16), rz, own, 0u);
+            uint32_t r = fmix32(t_key ^ (2u * cell + static_cast<uint32_t>(s)));
+            ST::bst(ST::enc_sr(rest(), a.scale, r), rz, own, 0u);
 #pragma unroll
             for (int i = 1; i <= 9; ++i) {
                 T pi, po;
                 pair(i, pi, po);
-                r = xorshift32(r);
-                ST::bst(ST::enc_sr(pi, a.scale, r & 0xffffu), rz, own, static_cast<uint32_t>(i) * dir_bytes);
-                ST::bst(ST::enc_sr(po, a.scale, r >> 16), rz, own, static_cast<uint32_t>(i + 9) * dir_bytes);
+                r = lcg24(r);
+                ST::bst(ST::enc_sr(pi, a.scale, r), rz, own, static_cast<uint32_t>(i) * dir_bytes);
+                r = lcg24(r);
+                ST::bst(ST::enc_sr(po, a.scale, r), rz, own, static_cast<uint32_t>(i + 9) * dir_bytes);
             }
         } else {
             ST::bst(ST::enc(rest(), a.scale), rz, own, 0u);
@@ -1545,12 +1547,12 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         };
         const rsrc_t rz = blk(B, z);
         // the random streams of the split kernels: per (cell, component)
-        // fmix32 of the counter, then one xorshift32 step per direction pair
+        // fmix32 of the counter, then one lcg24 step per stored value
         uint32_t r0 = 0, r1 = 0;
         if constexpr (RND != kRoundNearest) {
             const uint32_t cell = static_cast<uint32_t>(z) * static_cast<uint32_t>(plane) + static_cast<uint32_t>(y * a.nx + x);
-            r0 = fmix32(t_key ^ (2u * cell)) | 1u;
-            r1 = fmix32(t_key ^ (2u * cell + 1u)) | 1u;
+            r0 = fmix32(t_key ^ (2u * cell));
+            r1 = fmix32(t_key ^ (2u * cell + 1u));
         }
         const uint32_t sr_mask = RND == kRoundEither ? 0u - static_cast<uint32_t>(a.sr != 0) : 0u;
         auto word = [&](T v0, T v1, uint32_t ra, uint32_t rb) -> uint32_t {
@@ -1558,20 +1560,23 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
             else if constexpr (RND == kRoundNearest) return PC::enc(v0, v1);
             else return (PC::enc_sr(v0, v1, ra, rb) & sr_mask) | (PC::enc(v0, v1) & ~sr_mask);
         };
-        __builtin_amdgcn_raw_buffer_store_b32(word(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), r0 >> 16, r1 >> 16), rz, own,
-                                              0u, kNT);
+        __builtin_amdgcn_raw_buffer_store_b32(word(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), r0, r1), rz, own, 0u,
+                                              kNT);
 #pragma unroll
         for (int i = 1; i <= 9; ++i) {
             T pi0, po0, pi1, po1;
             pairdir(k0, g0, i, h0(i), h0(i + 9), pi0, po0);
             pairdir(k1, g1, i, h1(i), h1(i + 9), pi1, po1);
+            uint32_t ri0 = 0, ri1 = 0;
             if constexpr (RND != kRoundNearest) {
-                r0 = xorshift32(r0);
-                r1 = xorshift32(r1);
+                ri0 = lcg24(r0);
+                ri1 = lcg24(r1);
+                r0 = lcg24(ri0);
+                r1 = lcg24(ri1);
             }
-            __builtin_amdgcn_raw_buffer_store_b32(word(pi0, pi1, r0 & 0xffffu, r1 & 0xffffu), rz, own,
+            __builtin_amdgcn_raw_buffer_store_b32(word(pi0, pi1, ri0, ri1), rz, own,
                                                   static_cast<uint32_t>(i) * dir_bytes, kNT);
-            __builtin_amdgcn_raw_buffer_store_b32(word(po0, po1, r0 >> 16, r1 >> 16), rz, own,
+            __builtin_amdgcn_raw_buffer_store_b32(word(po0, po1, r0, r1), rz, own,
                                                   static_cast<uint32_t>(i + 9) * dir_bytes, kNT);
         }
     };
