@@ -100,7 +100,7 @@ def test_unsaturated_permeability_ratios_follow_table4(slopes):
 @pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
 def test_reduced_formats_keep_the_front_velocity(slopes, storage):
     """n_s,1 = 0.5 against the FP64 path; measured -0.05 % (FP32, FP16),
-    +0.02 % (BF16)."""
+    +0.05 % (BF16)."""
     got = _front_velocity(0.5, storage)[0]
     print(storage, got / slopes[0.5][0] - 1)
     assert abs(got / slopes[0.5][0] - 1) < 0.01
