@@ -190,6 +190,39 @@ template <typename ST>
 struct PairCodec {
     static __device__ __forceinline__ float lo(uint32_t v) { return ST::dec(static_cast<uint16_t>(v & 0xffffu), 1.0f); }
     static __device__ __forceinline__ float hi(uint32_t v) { return ST::dec(static_cast<uint16_t>(v >> 16), 1.0f); }
+    // x_H + y_H and x_H - y_H for the halves H (0 low, 1 high) of two words,
+    // each rounded once to FP32.  Binary16: one v_fma_mix_f32 (x * 1 + y with
+    // both sources converted from binary16 inside the instruction) instead of
+    // two conversions and an add; the result is the same, as the conversions
+    // are exact.  bfloat16 decodes with one shift or mask per value anyway.
+    template <int H>
+    static __device__ __forceinline__ float sum(uint32_t x, uint32_t y)
+    {
+        if constexpr (std::is_same_v<ST, F16>) {
+            float r;
+            if constexpr (H == 0)
+                asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(x), "v"(y));
+            else
+                asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(x), "v"(y));
+            return r;
+        } else {
+            return H == 0 ? lo(x) + lo(y) : hi(x) + hi(y);
+        }
+    }
+    template <int H>
+    static __device__ __forceinline__ float diff(uint32_t x, uint32_t y)
+    {
+        if constexpr (std::is_same_v<ST, F16>) {
+            float r;
+            if constexpr (H == 0)
+                asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(x), "v"(y));
+            else
+                asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(x), "v"(y));
+            return r;
+        } else {
+            return H == 0 ? lo(x) - lo(y) : hi(x) - hi(y);
+        }
+    }
     static __device__ __forceinline__ uint32_t enc(float a, float b)
     {
         if constexpr (std::is_same_v<ST, BF16>) {
@@ -1349,13 +1382,16 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         T j0[3] = {T(0), T(0), T(0)}, j1[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int i = 1; i <= 9; ++i) {
-            const T a0 = PC::lo(e[i]), b0 = PC::lo(e[i + 9]), a1 = PC::hi(e[i]), b1 = PC::hi(e[i + 9]);
-            s0 += a0 + b0;
-            s1 += a1 + b1;
+            // sums and differences of opposite populations, each rounded once
+            // (b - a is exactly -(a - b), so the sign goes into the update)
+            const T p0 = PC::template sum<0>(e[i], e[i + 9]), p1 = PC::template sum<1>(e[i], e[i + 9]);
+            s0 += p0;
+            s1 += p1;
             if (j) {
-                if (CX[i]) { j0[0] += CX[i] > 0 ? a0 - b0 : b0 - a0; j1[0] += CX[i] > 0 ? a1 - b1 : b1 - a1; }
-                if (CY[i]) { j0[1] += CY[i] > 0 ? a0 - b0 : b0 - a0; j1[1] += CY[i] > 0 ? a1 - b1 : b1 - a1; }
-                if (CZ[i]) { j0[2] += CZ[i] > 0 ? a0 - b0 : b0 - a0; j1[2] += CZ[i] > 0 ? a1 - b1 : b1 - a1; }
+                const T d0 = PC::template diff<0>(e[i], e[i + 9]), d1 = PC::template diff<1>(e[i], e[i + 9]);
+                if (CX[i]) { j0[0] = CX[i] > 0 ? j0[0] + d0 : j0[0] - d0; j1[0] = CX[i] > 0 ? j1[0] + d1 : j1[0] - d1; }
+                if (CY[i]) { j0[1] = CY[i] > 0 ? j0[1] + d0 : j0[1] - d0; j1[1] = CY[i] > 0 ? j1[1] + d1 : j1[1] - d1; }
+                if (CZ[i]) { j0[2] = CZ[i] > 0 ? j0[2] + d0 : j0[2] - d0; j1[2] = CZ[i] > 0 ? j1[2] + d1 : j1[2] - d1; }
             }
         }
         s0 *= a.inv_scale;
