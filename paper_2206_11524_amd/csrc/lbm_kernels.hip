@@ -1097,7 +1097,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
             collide(0, slot, slot, slot, js, h, false);
             return;
         }
-        if constexpr (sizeof(E) != 2) {
+        if constexpr (sizeof(E) == 8 || (sizeof(E) == 4 && (FS == kForcingGuo || CNS == 2))) {
             E rr[kQ];  // own populations of the next plane to stage, raw
             E er[kQ];  // ring populations of the plane being staged, raw
             // Stage plane p, whose own loads are in rr: ring loads and n_s are
@@ -1161,15 +1161,19 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                 collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hz, false);
             }
         } else {
-            // 16-bit storage: two roles, fixed per wave (NTC is a multiple of
-            // 64, and the ring lanes are the first of each component).  Waves
-            // holding ring lanes stage the ring densities as well and keep one
-            // plane of own loads in flight; the others, free of the ring loads,
-            // keep two (a wave has at most 63 memory operations outstanding,
-            // and the 16-bit loads carry half the bytes each).  Both roles run
-            // the same loop with one barrier per plane.  Wider formats keep one
-            // role: there the deeper prefetch did not pay.
-            constexpr bool kDeep = true;
+            // FP32 and 16-bit storage: two roles, fixed per wave (NTC is a
+            // multiple of 64, and the ring lanes are the first of each
+            // component).  Waves holding ring lanes stage the ring densities as
+            // well and keep one plane of own loads in flight; the others issue
+            // no ring loads (in the single-role sweep every lane loads a ring
+            // cell, duplicates included, to keep the waits exact) and, in
+            // 16-bit, keep two planes in flight (a wave has at most 63 memory
+            // operations outstanding, and the 16-bit loads carry half the
+            // bytes each; for FP32 the deeper prefetch did not pay).  Both
+            // roles run the same loop with one barrier per plane.  FP64, and
+            // FP32 with the GS-WBS or with two n_s fields, keep the
+            // single-role sweep, which was faster there.
+            constexpr bool kDeep = sizeof(E) == 2;
             auto sweep = [&](auto ring_tag) {
                 constexpr bool RING = decltype(ring_tag)::value;
                 constexpr bool DEEP = kDeep && !RING;
