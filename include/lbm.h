@@ -247,6 +247,39 @@ typedef struct {
 
 int lbm_permeability_get(lbm_ctx* ctx, int32_t axis, lbm_permeability* out);
 
+/* Static-droplet measurement of Sec. 3.3 (Laplace's law), FP64 on the device,
+ * from the current pre-collision state.  For a droplet (or bubble) of
+ * component comp centred at center (lattice coordinates; distances to the
+ * nearest periodic image of the centre):
+ *   rho_in  = mean rho_comp over |x - c| <= r_core (the bulk inside),
+ *   rho_out = mean rho_comp over |x - c| >= r_far (the bulk outside),
+ *   R       = radius of the volume V = (M_comp - rho_out N) / (rho_in -
+ *             rho_out), M_comp the component's mass: a ball in 3-D,
+ *             R = (3 V / (4 pi))^(1/3), a disc when nz = 1, R = (V / pi)^(1/2),
+ *   p_in    = mean pressure of Eq. (SC_pressure) over |x - c| <= R / 2,
+ *   p_out   = mean pressure over |x - c| >= R + margin,
+ *   dp      = p_in - p_out, and gamma = dp R / 2 in 3-D, dp R in 2-D (the
+ *             interfacial tension by Laplace's law).
+ * Synchronises.  LBM_EINVAL for NULL arguments, comp >= ncomp, a non-finite
+ * centre, r_core <= 0, r_far <= r_core, margin < 0, an empty averaging region,
+ * or no droplet (rho_in = rho_out, or V <= 0). */
+typedef struct {
+    double center[3];
+    double r_core, r_far;   /* radii of the inner and outer bulk samples */
+    double margin;          /* p_out is taken beyond R + margin          */
+    int32_t comp;
+    int32_t pad;
+} lbm_droplet_query;
+
+typedef struct {
+    double R, dp, gamma;
+    double p_in, p_out;
+    double rho_in, rho_out;
+    int64_t time;
+} lbm_droplet_state;
+
+int lbm_droplet_get(lbm_ctx* ctx, const lbm_droplet_query* q, lbm_droplet_state* out);
+
 /* Canonical populations (see above) of the current state into f [ncomp*19*N].
  * Reservoir cells hold their prescribed equilibrium.  Synchronises. */
 int lbm_get_populations(lbm_ctx* ctx, double* f);

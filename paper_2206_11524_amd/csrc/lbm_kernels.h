@@ -105,6 +105,13 @@ struct FillQuery {
 hipError_t launch_fill(const Problem& p, const FillQuery& q, const double* rho, const double* pr, const float* ns,
                        double* partials, double* out, hipStream_t st);
 
+// Static-droplet sums (Sec. 3.3) of the FP64 field f [N]: out[4] = {sum f
+// over |x - c| <= r_in, cells there, sum f over |x - c| >= r_out, cells
+// there}, distances to the nearest periodic image of c.  partials needs
+// 4 * moments_max_blocks() doubles.
+hipError_t launch_ball(const Problem& p, const double c[3], double r_in, double r_out, const double* f,
+                       double* partials, double* out, hipStream_t st);
+
 // Eq. (Permeability) sums from the FP64 densities rho and velocity u (after
 // the force pass): out[3] = {sum rho_0 u[axis], sum rho_1 u[axis], sum rho
 // u[axis]}.  partials needs 3 * moments_max_blocks() doubles.

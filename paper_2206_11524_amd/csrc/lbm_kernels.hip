@@ -2183,6 +2183,38 @@ __global__ __launch_bounds__(kRedThreads) void k_flux(int64_t N, int ncomp, int 
     block_sum<3>(acc, partials + static_cast<size_t>(blockIdx.x) * 3);
 }
 
+// Static-droplet measurement (Sec. 3.3) from an FP64 field f: per-block sums
+// of f and cell counts over the ball |x - c| <= sqrt(r_in2) and over the
+// cells with |x - c| >= sqrt(r_out2), distances taken to the nearest periodic
+// image of the centre c (2-D when nz = 1).
+__global__ __launch_bounds__(kRedThreads) void k_ball(int nx, int ny, int nz, int64_t N, double cx, double cy,
+                                                      double cz, double r_in2, double r_out2,
+                                                      const double* __restrict__ f, double* __restrict__ partials)
+{
+    double acc[4] = {0, 0, 0, 0};
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    CELL_LOOP(n, N)
+    {
+        const int z = static_cast<int>(n / plane);
+        const int ip = static_cast<int>(n - z * plane);
+        const int x = ip % nx, y = ip / nx;
+        double dx = x - cx, dy = y - cy, dz = z - cz;
+        dx -= nx * rint(dx / nx);
+        dy -= ny * rint(dy / ny);
+        dz -= nz * rint(dz / nz);
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 <= r_in2) {
+            acc[0] += f[n];
+            acc[1] += 1.0;
+        }
+        if (d2 >= r_out2) {
+            acc[2] += f[n];
+            acc[3] += 1.0;
+        }
+    }
+    block_sum<4>(acc, partials + static_cast<size_t>(blockIdx.x) * 4);
+}
+
 // Fixed-order sum of nblocks partials of K doubles each (one block): the
 // result does not depend on timing.
 template <int K>
@@ -2410,6 +2442,16 @@ hipError_t launch_fill(const Problem& p, const FillQuery& q, const double* rho, 
     hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kRedThreads), 0, st, p.nx, p.ny, p.nz, p.N, q, ns_field, rho, pr, ns,
                        partials);
     hipLaunchKernelGGL(k_reduce<6>, dim3(1), dim3(kRedThreads), 0, st, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ball(const Problem& p, const double c[3], double r_in, double r_out, const double* f,
+                       double* partials, double* out, hipStream_t st)
+{
+    const int nb = diag_blocks(p.N);
+    hipLaunchKernelGGL(k_ball, dim3(nb), dim3(kRedThreads), 0, st, p.nx, p.ny, p.nz, p.N, c[0], c[1], c[2],
+                       r_in * r_in, r_out * r_out, f, partials);
+    hipLaunchKernelGGL(k_reduce<4>, dim3(1), dim3(kRedThreads), 0, st, partials, nb, out);
     return hipGetLastError();
 }
 

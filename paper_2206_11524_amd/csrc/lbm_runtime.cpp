@@ -486,6 +486,51 @@ int lbm_permeability_get(lbm_ctx* c, int32_t axis, lbm_permeability* out)
     return LBM_OK;
 }
 
+int lbm_droplet_get(lbm_ctx* c, const lbm_droplet_query* q, lbm_droplet_state* out)
+{
+    if (!c || !q || !out || q->comp < 0 || q->comp >= c->prm.ncomp) return LBM_EINVAL;
+    for (double v : q->center)
+        if (!std::isfinite(v)) return LBM_EINVAL;
+    if (!(q->r_core > 0.0) || !(q->r_far > q->r_core) || !(q->margin >= 0.0) || !std::isfinite(q->r_far) ||
+        !std::isfinite(q->margin))
+        return LBM_EINVAL;
+    lbm_totals tot{};
+    const int rc = compute_totals(c, true, true, &tot);  // FP64 densities and pressure into the scratch
+    if (rc) return rc;
+    const int64_t N = c->prob.N;
+    const double* rho = reinterpret_cast<const double*>(c->scratch + c->sl.rho) + static_cast<size_t>(q->comp) * N;
+    const double* pr = reinterpret_cast<const double*>(c->scratch + c->sl.p);
+    double* part = reinterpret_cast<double*>(c->scratch + c->sl.partials);
+    double* tots = reinterpret_cast<double*>(c->scratch + c->sl.totals);
+    double h[4];
+    auto ball = [&](const double* f, double r_in, double r_out) -> int {
+        HIP_TRY(hm::launch_ball(c->prob, q->center, r_in, r_out, f, part, tots, c->stream));
+        HIP_TRY(hipMemcpyAsync(h, tots, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        return (h[1] > 0.0 && h[3] > 0.0) ? LBM_OK : LBM_EINVAL;
+    };
+    int r = ball(rho, q->r_core, q->r_far);
+    if (r) return r;
+    const double rho_in = h[0] / h[1], rho_out = h[2] / h[3];
+    if (!(std::fabs(rho_in - rho_out) > 0.0)) return LBM_EINVAL;
+    const double V = (tot.mass[q->comp] - rho_out * static_cast<double>(N)) / (rho_in - rho_out);
+    if (!(V > 0.0)) return LBM_EINVAL;
+    const bool two_d = c->dom.nz == 1;
+    const double pi = 3.14159265358979323846;
+    const double R = two_d ? std::sqrt(V / pi) : std::cbrt(3.0 * V / (4.0 * pi));
+    r = ball(pr, R / 2.0, R + q->margin);
+    if (r) return r;
+    out->R = R;
+    out->rho_in = rho_in;
+    out->rho_out = rho_out;
+    out->p_in = h[0] / h[1];
+    out->p_out = h[2] / h[3];
+    out->dp = out->p_in - out->p_out;
+    out->gamma = two_d ? out->dp * R : out->dp * R / 2.0;
+    out->time = c->t;
+    return LBM_OK;
+}
+
 int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
 
 int lbm_set_time(lbm_ctx* c, int64_t t)

@@ -70,6 +70,16 @@ class Permeability(C.Structure):
                 ("time", C.c_int64)]
 
 
+class DropletQuery(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("r_core", C.c_double), ("r_far", C.c_double), ("margin", C.c_double),
+                ("comp", C.c_int32), ("pad", C.c_int32)]
+
+
+class DropletState(C.Structure):
+    _fields_ = [("R", C.c_double), ("dp", C.c_double), ("gamma", C.c_double), ("p_in", C.c_double),
+                ("p_out", C.c_double), ("rho_in", C.c_double), ("rho_out", C.c_double), ("time", C.c_int64)]
+
+
 class Totals(C.Structure):
     _fields_ = [("mass", C.c_double * 2), ("momentum", C.c_double * 3), ("time", C.c_int64),
                 ("finite", C.c_int32), ("pad", C.c_int32)]
@@ -88,6 +98,7 @@ SIGNATURES = {
     "lbm_totals_get_static": (C.c_int, [C.c_void_p, C.POINTER(Totals)]),
     "lbm_fill_state_get": (C.c_int, [C.c_void_p, C.POINTER(FillQuery), C.POINTER(FillState)]),
     "lbm_permeability_get": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Permeability)]),
+    "lbm_droplet_get": (C.c_int, [C.c_void_p, C.POINTER(DropletQuery), C.POINTER(DropletState)]),
     "lbm_get_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_set_populations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_set_reservoir": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
@@ -274,6 +285,14 @@ class Simulation:
         _check(self.lib.lbm_permeability_get(self.ctx, axis, C.byref(out)), "lbm_permeability_get")
         return {"k": out.k, "k_comp": (out.k_comp[0], out.k_comp[1]), "momentum": out.momentum, "nu": out.nu,
                 "time": out.time}
+
+    def droplet(self, center, r_core, r_far, margin=4.0, comp=0):
+        """Static-droplet measurement (Sec. 3.3, see ``lbm_droplet_get``):
+        radius from the component's volume, pressure jump and interfacial tension."""
+        q = DropletQuery((C.c_double * 3)(*center), r_core, r_far, margin, comp, 0)
+        out = DropletState()
+        _check(self.lib.lbm_droplet_get(self.ctx, C.byref(q), C.byref(out)), "lbm_droplet_get")
+        return {k: getattr(out, k) for k, _ in DropletState._fields_}
 
     def populations(self) -> np.ndarray:
         nx, ny, nz = self.shape

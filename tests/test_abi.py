@@ -101,7 +101,8 @@ def test_invalid_server_config_rejected(lib, field, value):
 
 
 _STRUCTS = ["lbm_domain", "lbm_reservoir", "lbm_params", "lbm_sizes", "lbm_device_buffers", "lbm_totals",
-            "lbm_fill_query", "lbm_fill_state", "lbm_permeability", "lbm_server_cfg", "lbm_request",
+            "lbm_fill_query", "lbm_fill_state", "lbm_permeability", "lbm_droplet_query", "lbm_droplet_state",
+            "lbm_server_cfg", "lbm_request",
             "lbm_result", "lbm_server_stats"]
 
 
@@ -109,7 +110,8 @@ def _ctypes_of(name):
     return {"lbm_domain": lbm.Domain, "lbm_reservoir": lbm.Reservoir, "lbm_params": lbm.Params,
             "lbm_sizes": lbm.Sizes, "lbm_device_buffers": lbm.DeviceBuffers, "lbm_totals": lbm.Totals,
             "lbm_fill_query": lbm.FillQuery, "lbm_fill_state": lbm.FillState,
-            "lbm_permeability": lbm.Permeability,
+            "lbm_permeability": lbm.Permeability, "lbm_droplet_query": lbm.DropletQuery,
+            "lbm_droplet_state": lbm.DropletState,
             "lbm_server_cfg": lbm.ServerCfg, "lbm_request": lbm.Request, "lbm_result": lbm.Result,
             "lbm_server_stats": lbm.ServerStats}[name]
 
@@ -195,6 +197,11 @@ def test_fill_query_rejected_without_context(lib):
 def test_permeability_rejected_without_context(lib):
     out = lbm.Permeability()
     assert lib.lbm_permeability_get(None, 0, C.byref(out)) == lbm.LBM_EINVAL
+
+
+def test_droplet_query_rejected_without_context(lib):
+    q, out = lbm.DropletQuery((C.c_double * 3)(8, 8, 8), 2.0, 6.0, 4.0, 0, 0), lbm.DropletState()
+    assert lib.lbm_droplet_get(None, C.byref(q), C.byref(out)) == lbm.LBM_EINVAL
 
 
 def test_null_context_calls_are_rejected(lib):

@@ -7,8 +7,8 @@ Droplets of initial radius 8 .. 14 in a periodic 64^3 box, G = 0.9 (stencil
 weights sum_i W_i c_i c_i = I), FP32, 20 000 steps (the droplets swell from
 the initial 1.0 / 0.03 densities towards coexistence while the test runs; the
 law holds at every state).  R from the volume of component A, dp from the
-pressure of Eq. (SC_pressure) inside R/2 and beyond R + 4, as in the droplet
-parity checks.  Measured spread of dp R / 2 over the radii: 0.6 % (n_s = 0);
+pressure of Eq. (SC_pressure) inside R/2 and beyond R + 4, measured on the
+device by lbm_droplet_get.  Measured spread of dp R / 2 over the radii: 0.6 % (n_s = 0);
 gamma at n_s = 0.1 and 0.5 within 0.3 % and 3.2 % of n_s = 0 (a gray medium
 relaxes more slowly).
 """
@@ -30,23 +30,14 @@ def _gpu():
     yield
 
 
-def _radius_and_jump(m, n):
-    c = (n - 1) / 2
-    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
-    d = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
-    rA = m["rho"][0]
-    rin, rout = rA[d <= 3].mean(), rA[d >= n / 2 - 1].mean()
-    R = (3 * (rA.sum() - rout * n ** 3) / (rin - rout) / (4 * np.pi)) ** (1 / 3)
-    dp = m["p"][d <= R / 2].mean() - m["p"][d >= R + 4].mean()
-    return R, dp
-
-
 def _gamma(r0, ns_value):
     sim = lbm.from_workload(inputs.droplet(n=N, radius=r0, ns_value=ns_value), storage="f32")
     sim.step(STEPS)
-    R, dp = _radius_and_jump(sim.moments(), N)
+    c = (N - 1) / 2
+    d = sim.droplet((c, c, c), r_core=3.0, r_far=N / 2 - 1, margin=4.0, comp=0)
     sim.close()
-    return R, dp
+    assert abs(d["gamma"] - d["dp"] * d["R"] / 2) <= 1e-15
+    return d["R"], d["dp"]
 
 
 def test_pressure_jump_scales_as_inverse_radius():

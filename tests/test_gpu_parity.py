@@ -229,6 +229,33 @@ def test_droplet_observables_reduced_precision(storage, rounding, tol):
     assert abs(dp1 * R1 / (dp0 * R0) - 1) < 0.01
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16s"])
+def test_droplet_measurement_on_the_device(storage):
+    """lbm_droplet_get (radius from the component volume, p_in, p_out, dp and
+    gamma = dp R / 2, all reduced in FP64 on the device) against the same
+    formulas evaluated in numpy on the copied moments of the same state; the
+    two differ only in summation order.  Bad queries are rejected."""
+    w = inputs.droplet()
+    sim = lbm.from_workload(w, storage=storage)
+    sim.step(300)
+    m = sim.moments()
+    c = (32 - 1) / 2
+    got = sim.droplet((c, c, c), r_core=3.0, r_far=32 / 2 - 1, margin=4.0, comp=0)
+    R, dp = _droplet_observables(m, 32)
+    print(storage, got, "numpy", R, dp)
+    assert got["time"] == 300
+    assert abs(got["R"] - R) <= 1e-10 * R
+    assert abs(got["dp"] - dp) <= 1e-10 * abs(dp) + 1e-14
+    assert abs(got["gamma"] - got["dp"] * got["R"] / 2) <= 1e-15
+    assert got["rho_in"] > got["rho_out"] and got["p_in"] > got["p_out"]
+    for bad in [dict(r_core=0.0), dict(r_far=2.0), dict(margin=-1.0), dict(comp=2), dict(r_far=1e9)]:
+        kw = dict(r_core=3.0, r_far=15.0, margin=4.0, comp=0)
+        kw.update(bad)
+        with pytest.raises(lbm.LbmError):
+            sim.droplet((c, c, c), **kw)
+    sim.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
 def test_full_bounce_back_period_two_bitwise(storage):
     w = inputs.random_state((66, 9, 6), 7, ns_choices=[1.0], rho_range=(0.2, 0.8))
