@@ -122,6 +122,8 @@ def _bubble_gamma_gpu(G, H=100, R0=25.0, steps=8000, ns_value=0.0):
     sim = lbm.from_workload(w, storage="f64")
     sim.step(steps)
     m = sim.moments()
+    # the same measurement on the device (the 2-D branch of lbm_droplet_get)
+    dev = sim.droplet((c, c, 0.0), r_core=R0 / 2, r_far=R0 + 8, margin=6.0, comp=0)
     sim.close()
     r1, p = m["rho"][0, 0], m["p"][0]
     dx = np.minimum(np.abs(x - c), H - np.abs(x - c))
@@ -130,6 +132,8 @@ def _bubble_gamma_gpu(G, H=100, R0=25.0, steps=8000, ns_value=0.0):
     rin, rout = r1[d <= R0 / 2].mean(), r1[dmin >= R0 + 8].mean()
     R = np.sqrt((r1.sum() - rout * H * H) / (rin - rout) / np.pi)
     dp = p[d <= R / 2].mean() - p[dmin >= R + 6].mean()
+    assert abs(dev["R"] - R) <= 1e-10 * R and abs(dev["dp"] - dp) <= 1e-10 * abs(dp) + 1e-14, (dev, R, dp)
+    assert abs(dev["gamma"] - dev["dp"] * dev["R"]) <= 1e-15
     return dp * R, R
 
 
