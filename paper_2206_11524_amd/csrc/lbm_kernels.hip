@@ -1315,9 +1315,14 @@ struct PairShared {
 
 constexpr int kPairRing = 192;  // ring / n_s threads per block (three waves)
 #ifndef LBM_PAIR_TY
-#define LBM_PAIR_TY 9
+#define LBM_PAIR_TY 8
 #endif
-constexpr int kPairTY = LBM_PAIR_TY;  // rows of the default pair tile (64 x kPairTY cells)
+// Rows of the default pair tile (64 x kPairTY cells).  With eight rows the
+// block has eight cell waves, an even share for each of a CU's four SIMDs (nine
+// leave one SIMD a third collision per plane), and a 256 x 256 plane splits
+// into 128 tile columns, so two z-chunks per column give one block for each of
+// 256 CUs (nine rows: 116 columns, 232 blocks).
+constexpr int kPairTY = LBM_PAIR_TY;
 
 // Planes a cell wave keeps in flight ahead of the one it stages (1 or 2).
 #ifndef LBM_PAIR_AHEAD
