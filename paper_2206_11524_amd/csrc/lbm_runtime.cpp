@@ -115,26 +115,30 @@ hm::Launch choose_launch(const hm::Problem& p, int cus)
     const int64_t cols = static_cast<int64_t>(ntx) * nty;
     int zc = env_int("LBM_ZCHUNK", 0);
     if (zc <= 0) {
-        // One block fits a CU (registers and LDS), so aim at one z-chunk per
-        // CU and column: every block is resident from the start and none
-        // waits for a CU to free up.  Chunks shorter than 16 planes spend
-        // too much on their two halo planes, unless the domain would then
-        // give fewer than two such tiles per CU: a small domain would leave
-        // most CUs idle, and its halo re-reads are L2 hits.
+        // One block fits a CU (registers and LDS), so blocks run in rounds
+        // of one per CU, and a block takes about (chunk + 8) plane times: the
+        // halo planes, the pipeline fill and drain and the block's start cost
+        // as much as about eight planes (fitted to timings of 192^3 to 384^3
+        // domains).  Take the chunking with the least rounds x (chunk + 8),
+        // the fewest chunks among equals.
+        // Chunks shorter than 16 planes spend too much on their halo, unless
+        // the domain would then give fewer than two such tiles per CU: a
+        // small domain would leave most CUs idle, and its halo re-reads are
+        // L2 hits.
         const int64_t ncu = std::max(cus, 1);
         const int64_t tiles16 = cols * ((p.nz + 15) / 16);
         const int64_t min_chunk = tiles16 >= 2 * ncu ? 16 : 4;
-        const int64_t chunks = std::max<int64_t>(1, ncu / cols);
-        zc = static_cast<int>(std::max<int64_t>(min_chunk, (p.nz + chunks - 1) / chunks));
-        // Blocks run in waves of one per CU.  If the last wave leaves more
-        // than a fifth of the CUs idle (e.g. 144 columns on 256 CUs), take
-        // the fewest further chunks per column that fill 80 %.
-        auto fill = [&](int64_t z) {
+        int64_t best_cost = -1;
+        for (int64_t c = 1; c <= p.nz; ++c) {
+            const int64_t z = (p.nz + c - 1) / c;
+            if (c > 1 && z < min_chunk) break;
             const int64_t blocks = cols * ((p.nz + z - 1) / z);
-            return static_cast<double>(blocks) / static_cast<double>(((blocks + ncu - 1) / ncu) * ncu);
-        };
-        for (int64_t c = chunks + 1; fill(zc) < 0.8 && (p.nz + c - 1) / c >= min_chunk; ++c)
-            if (fill((p.nz + c - 1) / c) >= 0.8) zc = static_cast<int>((p.nz + c - 1) / c);
+            const int64_t cost = ((blocks + ncu - 1) / ncu) * (z + 8);
+            if (best_cost < 0 || cost < best_cost) {
+                best_cost = cost;
+                zc = static_cast<int>(z);
+            }
+        }
     }
     l.zchunk = std::min(std::max(zc, 1), p.nz);
     return l;
