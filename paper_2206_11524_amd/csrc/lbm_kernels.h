@@ -38,13 +38,13 @@ struct Problem {
 struct Launch {
     int tile_x;   // cells per tile row (32, 64 or 128)
     int tile_y;   // rows per tile (split layout: 4 with 128-wide rows, 4 or 8 with 64, 4, 8
-                  // or 16 with 32; pair layout: 4, 8 or 16 with 64)
+                  // or 16 with 32; pair layout: 4 or pair_tile_y() with 64)
     int zchunk;   // planes per block
 };
 
 // True if two components in this format use the pair layout: both values of
-// one (cell, direction) in one 32-bit word, plane blocks [z][i][y][x][s]; all
-// other runs use the split layout [s][z][i][y][x].
+// one (cell, direction) in one word (FP32 and the 16-bit formats), plane
+// blocks [z][i][y][x][s]; all other runs use the split layout [s][z][i][y][x].
 bool pair_layout(int storage, int ncomp);
 
 // Rows of the default tile of the pair kernel (64 cells wide).

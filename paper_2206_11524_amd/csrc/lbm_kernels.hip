@@ -2,10 +2,11 @@
 //
 // Layout in HBM: populations are grouped by plane.  For one component the 19
 // direction arrays of plane z lie next to each other, P[((s*nz + z)*19 + i)*
-// plane + n], n = y*nx + x the in-plane index ("split" layout, FP64, FP32 and
-// single-component runs).  Two-component runs in the 16-bit formats keep the
-// two components of one (cell, direction) in one 32-bit word, P[(((z*19 + i)*
-// plane + n) << 1) + s] ("pair" layout), so one 4-byte load brings both.
+// plane + n], n = y*nx + x the in-plane index ("split" layout, FP64 and
+// single-component runs).  Two-component runs in FP32 and the 16-bit formats
+// keep the two components of one (cell, direction) in one word (64 or 32
+// bits), P[(((z*19 + i)*plane + n) << 1) + s] ("pair" layout), so one load
+// brings both.
 // Streaming is "pull": a buffer holds the populations that left each cell at
 // the previous step, so the pre-collision state of Eq. (LGS) at cell x is
 // f_i(x) = P_i(x - c_i) (periodic).  Every stored value is shifted,
@@ -250,6 +251,56 @@ struct PairCodec {
         }
     }
 };
+
+// FP32 pair words: component 0 in the low, component 1 in the high 32 bits
+// (stored as they are, rounded to nearest by the collision's arithmetic).
+template <>
+struct PairCodec<F32> {
+    static __device__ __forceinline__ float lo(u32x2 v) { return __uint_as_float(v.x); }
+    static __device__ __forceinline__ float hi(u32x2 v) { return __uint_as_float(v.y); }
+    template <int H>
+    static __device__ __forceinline__ float sum(u32x2 x, u32x2 y)
+    {
+        return H == 0 ? lo(x) + lo(y) : hi(x) + hi(y);
+    }
+    template <int H>
+    static __device__ __forceinline__ float diff(u32x2 x, u32x2 y)
+    {
+        return H == 0 ? lo(x) - lo(y) : hi(x) - hi(y);
+    }
+    static __device__ __forceinline__ u32x2 enc(float a, float b)
+    {
+        u32x2 w;
+        w.x = __float_as_uint(a);
+        w.y = __float_as_uint(b);
+        return w;
+    }
+};
+
+// Word of the pair layout: both components of one (cell, direction), 32 bits
+// for the 16-bit formats, 64 bits for FP32.
+template <typename ST>
+struct PairWordOf {
+    using W = uint32_t;
+};
+template <>
+struct PairWordOf<F32> {
+    using W = u32x2;
+};
+
+template <typename W>
+__device__ __forceinline__ W word_load(rsrc_t r, uint32_t vo, uint32_t so)
+{
+    if constexpr (sizeof(W) == 8) return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    else return __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+}
+
+template <typename W>
+__device__ __forceinline__ void word_store(W v, rsrc_t r, uint32_t vo, uint32_t so)
+{
+    if constexpr (sizeof(W) == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, kNT);
+    else __builtin_amdgcn_raw_buffer_store_b32(v, r, vo, so, kNT);
+}
 
 // Kernel parameters in the arithmetic type.
 template <typename T>
@@ -1097,7 +1148,7 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
             collide(0, slot, slot, slot, js, h, false);
             return;
         }
-        if constexpr (sizeof(E) == 8 || (sizeof(E) == 4 && (FS == kForcingGuo || CNS == 2))) {
+        if constexpr (sizeof(E) == 8 || (sizeof(E) == 4 && FS == kForcingGuo)) {
             E rr[kQ];  // own populations of the next plane to stage, raw
             E er[kQ];  // ring populations of the plane being staged, raw
             // Stage plane p, whose own loads are in rr: ring loads and n_s are
@@ -1161,104 +1212,72 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
                 collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hz, false);
             }
         } else {
-            // FP32 and 16-bit storage: two roles, fixed per wave (NTC is a
-            // multiple of 64, and the ring lanes are the first of each
-            // component).  Waves holding ring lanes stage the ring densities as
-            // well and keep one plane of own loads in flight; the others issue
-            // no ring loads (in the single-role sweep every lane loads a ring
-            // cell, duplicates included, to keep the waits exact) and, in
-            // 16-bit, keep two planes in flight (a wave has at most 63 memory
-            // operations outstanding, and the 16-bit loads carry half the
-            // bytes each; for FP32 the deeper prefetch did not pay).  Both
-            // roles run the same loop with one barrier per plane.  FP64, and
-            // FP32 with the GS-WBS or with two n_s fields, keep the
-            // single-role sweep, which was faster there.
-            constexpr bool kDeep = sizeof(E) == 2;
-            auto sweep = [&](auto ring_tag) {
-                constexpr bool RING = decltype(ring_tag)::value;
-                constexpr bool DEEP = kDeep && !RING;
-                constexpr int AHEAD = DEEP ? 2 : 1;  // planes between issue and consumption
-                E rA[kQ];
-                E rB[DEEP ? kQ : 1];
-                E er[RING ? kQ : 1];
-                // Stage plane p, whose own loads are in rc: (ring loads and) n_s
-                // are issued first; the own values give the density and first
-                // moments and go to hs, whose previous content (the plane before)
-                // moves to hz; then the own loads of plane pn are issued into rc,
-                // and only after them the ring values are consumed, so a wait for
-                // the ring does not wait for plane pn.
-                auto stage_pipe = [&](int p, int slot, int js, int pn, T hz[kQ], E rc[kQ]) {
-                    if constexpr (RING) issue(p, qr, er);
-                    const float* nsp = ns + static_cast<size_t>(p) * plane;
-                    float nsv[NSMAX][CNS];
-    #pragma unroll
-                    for (int k = 0; k < NSMAX; ++k)
-    #pragma unroll
-                        for (int c = 0; c < CNS; ++c) nsv[k][c] = nsp[static_cast<size_t>(c) * a.N + no[k]];
-                    __builtin_amdgcn_sched_barrier(0);
-                    {
-                        T h[kQ];
-    #pragma unroll
-                        for (int i = 0; i < kQ; ++i) h[i] = ST::dec(rc[i], a.inv_scale);
-                        reservoir_override(x, y, p, h);
-                        s_rho[slot][s][me] = a.rho0[s] + sum19(h);
-                        if (NC == 2 && js >= 0) {
-                            s_j[js][s][0][tj] = first_moment<T, 0>(h);
-                            s_j[js][s][1][tj] = first_moment<T, 1>(h);
-                            s_j[js][s][2][tj] = first_moment<T, 2>(h);
-                        }
-    #pragma unroll
-                        for (int i = 0; i < kQ; ++i) {
-                            hz[i] = hs[i * NT_];
-                            hs[i * NT_] = h[i];
-                        }
+            // One component in FP32 or a 16-bit format (two components run
+            // the pair kernel): no ring, and in 16-bit two planes of own loads
+            // in flight (a wave has at most 63 memory operations outstanding,
+            // and the 16-bit loads carry half the bytes each; for FP32 the
+            // deeper prefetch did not pay).
+            static_assert(NC == 1, "two components in FP32 or 16-bit run the pair kernel");
+            constexpr bool DEEP = sizeof(E) == 2;
+            constexpr int AHEAD = DEEP ? 2 : 1;  // planes between issue and consumption
+            E rA[kQ];
+            E rB[DEEP ? kQ : 1];
+            // Stage plane p, whose own loads are in rc: the n_s loads are
+            // issued first; the own values give the density and go to hs,
+            // whose previous content (the plane before) moves to hz; then the
+            // own loads of plane pn are issued into rc.
+            auto stage_pipe = [&](int p, int slot, int pn, T hz[kQ], E rc[kQ]) {
+                const float* nsp = ns + static_cast<size_t>(p) * plane;
+                float nsv[NSMAX][CNS];
+#pragma unroll
+                for (int k = 0; k < NSMAX; ++k)
+#pragma unroll
+                    for (int c = 0; c < CNS; ++c) nsv[k][c] = nsp[static_cast<size_t>(c) * a.N + no[k]];
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    T h[kQ];
+#pragma unroll
+                    for (int i = 0; i < kQ; ++i) h[i] = ST::dec(rc[i], a.inv_scale);
+                    reservoir_override(x, y, p, h);
+                    s_rho[slot][s][me] = a.rho0[s] + sum19(h);
+#pragma unroll
+                    for (int i = 0; i < kQ; ++i) {
+                        hz[i] = hs[i * NT_];
+                        hs[i * NT_] = h[i];
                     }
-                    __builtin_amdgcn_sched_barrier(0);
-                    issue(pn, qme, rc);
-                    __builtin_amdgcn_sched_barrier(0);
-                    if constexpr (RING) {
-                        if (ring) {
-                            T hr[kQ];
-    #pragma unroll
-                            for (int i = 0; i < kQ; ++i) hr[i] = ST::dec(er[i], a.inv_scale);
-                            reservoir_override(rx, ry, p, hr);
-                            s_rho[slot][s][rme] = a.rho0[s] + sum19(hr);
-                        }
-                    }
-    #pragma unroll
-                    for (int k = 0; k < NSMAX; ++k)
-    #pragma unroll
-                        for (int c = 0; c < CNS; ++c) s_ns[slot][c][nl[k]] = nsv[k][c];
-                };
-                // the plane whose loads a stage of plane p issues: p + AHEAD, or
-                // after the last plane one already staged again (L2 hits)
-                auto ahead = [&](int p) { return wrapz(p + AHEAD <= ze ? p + AHEAD : ze); };
-                // register sets: planes zs-1, zs+1, ... in r_odd, planes zs, zs+2, ...
-                // in r_even (one and the same set unless two planes are in flight)
-                E (&r_odd)[kQ] = rA;
-                E (&r_even)[kQ] = *reinterpret_cast<E(*)[kQ]>(DEEP ? static_cast<E*>(rB) : static_cast<E*>(rA));
-
-                T hz[kQ];
-                // prologue: planes zs-1 (densities only) and zs (to hs)
-                issue(wrapz(zs - 1), qme, r_odd);
-                if constexpr (DEEP) issue(zs, qme, r_even);
-                stage_pipe(wrapz(zs - 1), rslot(zs - 1), -1, ahead(zs - 1), hz, r_odd);
-                stage_pipe(zs, rslot(zs), jslot(zs), ahead(zs), hz, r_even);
-                // unrolled by two so the register sets keep fixed names; every
-                // wave, in either role, passes ze - zs barriers
-                for (int z = zs; z < ze; z += 2) {
-                    stage_pipe(wrapz(z + 1), rslot(z + 1), jslot(z + 1), ahead(z + 1), hz, r_odd);
-                    __syncthreads();
-                    collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hz, false);
-                    if (z + 1 >= ze) break;
-                    stage_pipe(wrapz(z + 2), rslot(z + 2), jslot(z + 2), ahead(z + 2), hz, r_even);
-                    __syncthreads();
-                    collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), jslot(z + 1), hz, false);
                 }
+                __builtin_amdgcn_sched_barrier(0);
+                issue(pn, qme, rc);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < NSMAX; ++k)
+#pragma unroll
+                    for (int c = 0; c < CNS; ++c) s_ns[slot][c][nl[k]] = nsv[k][c];
             };
-            const bool wave_ring = NC == 2 && __builtin_amdgcn_ballot_w64(ring) != 0;
-            if (wave_ring) sweep(std::true_type{});
-            else sweep(std::false_type{});
+            // the plane whose loads a stage of plane p issues: p + AHEAD, or
+            // after the last plane one already staged again (L2 hits)
+            auto ahead = [&](int p) { return wrapz(p + AHEAD <= ze ? p + AHEAD : ze); };
+            // register sets: planes zs-1, zs+1, ... in r_odd, planes zs, zs+2, ...
+            // in r_even (one and the same set unless two planes are in flight)
+            E (&r_odd)[kQ] = rA;
+            E (&r_even)[kQ] = *reinterpret_cast<E(*)[kQ]>(DEEP ? static_cast<E*>(rB) : static_cast<E*>(rA));
+
+            T hz[kQ];
+            // prologue: planes zs-1 (densities only) and zs (to hs)
+            issue(wrapz(zs - 1), qme, r_odd);
+            if constexpr (DEEP) issue(zs, qme, r_even);
+            stage_pipe(wrapz(zs - 1), rslot(zs - 1), ahead(zs - 1), hz, r_odd);
+            stage_pipe(zs, rslot(zs), ahead(zs), hz, r_even);
+            // unrolled by two so the register sets keep fixed names
+            for (int z = zs; z < ze; z += 2) {
+                stage_pipe(wrapz(z + 1), rslot(z + 1), ahead(z + 1), hz, r_odd);
+                __syncthreads();
+                collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jslot(z), hz, false);
+                if (z + 1 >= ze) break;
+                stage_pipe(wrapz(z + 2), rslot(z + 2), ahead(z + 2), hz, r_even);
+                __syncthreads();
+                collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), jslot(z + 1), hz, false);
+            }
         }
     } else {
         T hA[kQ];
@@ -1282,14 +1301,14 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
 }
 
 // ---------------------------------------------------------------------------
-// Pair kernel: two components in a 16-bit format, one thread per cell.
+// Pair kernel: two components in FP32 or a 16-bit format, one thread per cell.
 //
-// In the pair layout one 32-bit word holds both components' value of one
-// (cell, direction), so a thread pulls its cell's 38 populations with 19
-// 4-byte loads and stores them with 19 4-byte stores.  Per memory operation
-// that moves twice the bytes of a lone 16-bit value, which doubles the bytes
-// a wave keeps in flight under the same limit on outstanding operations (the
-// limit that bounds a 16-bit kernel with one value per lane).  The two
+// In the pair layout one word (32 bits for the 16-bit formats, 64 for FP32)
+// holds both components' value of one (cell, direction), so a thread pulls
+// its cell's 38 populations with 19 loads and stores them with 19 stores.
+// Per memory operation that moves twice the bytes of a lone value, which
+// doubles the bytes a wave keeps in flight under the same limit on
+// outstanding operations and halves the memory instructions per cell.  The two
 // components of a cell meet in registers, so the first moments need no LDS
 // exchange; the densities still go to LDS for the force stencils.
 //
@@ -1300,17 +1319,21 @@ __device__ __forceinline__ void step_tile(const Args<typename ST::T>& a, const t
 // so the cell waves keep their registers for the prefetch.
 //
 // LDS: four density / n_s plane slots (plane p in slot p mod 4, one barrier
-// per plane) and the raw words of the last two planes staged, private to each
-// cell thread: the collision reads its plane's words from LDS, so no register
-// holds them while the next plane's loads are in flight.
-template <int CNS, int TX, int TY>
+// per plane) and the raw words of the last planes staged, private to each
+// cell thread.  16-bit: two planes, and the collision reads its plane's words
+// from LDS, so no register holds them while two planes of loads are in
+// flight.  FP32: one plane (its words take twice the room), the plane being
+// collided in registers, one plane of loads in flight.
+template <typename ST, int CNS, int TX, int TY>
 struct PairShared {
+    using W = typename PairWordOf<ST>::W;
     static constexpr int LW = TX + 2;
     static constexpr int LP = LW * (TY + 2);
     static constexpr int NT = TX * TY;
+    static constexpr int NB = sizeof(W) == 4 ? 2 : 1;  // planes of words held in LDS
     float rho[4][2][LP];
     float ns[4][CNS][LP];
-    uint32_t hs[2][kQ][NT];
+    W hs[NB][kQ][NT];
 };
 
 constexpr int kPairRing = 192;  // ring / n_s threads per block (three waves)
@@ -1339,11 +1362,14 @@ constexpr int kPairTY = LBM_PAIR_TY;
 constexpr int kRoundNearest = 0, kRoundStochastic = 1, kRoundEither = 2;
 
 template <typename ST, int CNS, int TX, int TY, int FS, bool ONE, int RND>
-__device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint32_t* __restrict__ A,
-                                               uint32_t* __restrict__ B, const float* __restrict__ ns, int L,
-                                               uint32_t t, PairShared<CNS, TX, TY>& sh)
+__device__ __forceinline__ void step_tile_pair(const Args<float>& a,
+                                               const typename PairWordOf<ST>::W* __restrict__ A,
+                                               typename PairWordOf<ST>::W* __restrict__ B,
+                                               const float* __restrict__ ns, int L, uint32_t t,
+                                               PairShared<ST, CNS, TX, TY>& sh)
 {
     using T = float;
+    using W = typename PairWordOf<ST>::W;
     using PC = PairCodec<ST>;
     constexpr int LW = TX + 2;
     constexpr int LP = LW * (TY + 2);
@@ -1368,17 +1394,16 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
 
     auto wrapz = [&](int p) { return p < 0 ? p + a.nz : (p >= a.nz ? p - a.nz : p); };
     // one buffer descriptor per plane block of 19 direction arrays of words
-    const uint32_t dir_bytes = static_cast<uint32_t>(plane) * 4u;
+    const uint32_t dir_bytes = static_cast<uint32_t>(plane) * static_cast<uint32_t>(sizeof(W));
     const uint32_t blk_bytes = static_cast<uint32_t>(kQ) * dir_bytes;
-    auto blk = [&](const uint32_t* base, int p) {
+    auto blk = [&](const W* base, int p) {
         return make_rsrc(base + static_cast<size_t>(p) * kQ * static_cast<size_t>(plane), blk_bytes);
     };
-    auto issue = [&](int p, const PlaneOffs& q, uint32_t e[kQ]) {
+    auto issue = [&](int p, const PlaneOffs& q, W e[kQ]) {
         const rsrc_t r3[3] = {blk(A, wrapz(p + 1)), blk(A, p), blk(A, wrapz(p - 1))};  // c_z = -1, 0, +1
 #pragma unroll
         for (int i = 0; i < kQ; ++i)
-            e[i] = __builtin_amdgcn_raw_buffer_load_b32(r3[CZ[i] + 1], q.o[CY[i] + 1][CX[i] + 1],
-                                                        static_cast<uint32_t>(i) * dir_bytes, 0);
+            e[i] = word_load<W>(r3[CZ[i] + 1], q.o[CY[i] + 1][CX[i] + 1], static_cast<uint32_t>(i) * dir_bytes);
     };
     // densities rho_0, rho_1 of a cell from its raw words, and with MOM its
     // first moments (Eq. mom_BGK) too; a reservoir cell has the Dirichlet
@@ -1386,7 +1411,7 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
     // w_i dr (computed only when a lane of the wave is in a reservoir), and
     // first moments 0 (w_i = w_ibar).  The words are decoded into the running
     // sums, never held as 38 floats.
-    auto moments = [&](uint32_t rbits, const uint32_t e[kQ], T& r0, T& r1, T* j) {
+    auto moments = [&](uint32_t rbits, const W e[kQ], T& r0, T& r1, T* j) {
         T s0 = PC::lo(e[0]), s1 = PC::hi(e[0]);
         T j0[3] = {T(0), T(0), T(0)}, j1[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -1429,7 +1454,7 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         r0 = a.rho0[0] + s0;
         r1 = a.rho0[1] + s1;
     };
-    auto densities = [&](uint32_t rbits, const uint32_t e[kQ], T& r0, T& r1) {
+    auto densities = [&](uint32_t rbits, const W e[kQ], T& r0, T& r1) {
         moments(rbits, e, r0, r1, static_cast<T*>(nullptr));
     };
     auto rslot = [&](int p) { return (p - zs + 1) & 3; };
@@ -1450,7 +1475,7 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         const int rx = ((x0 + rlx) % a.nx + a.nx) % a.nx;
         const int ry = ((y0 + rly) % a.ny + a.ny) % a.ny;
         const int rme = (rly + 1) * LW + (rlx + 1);
-        const PlaneOffs qring = plane_offs<4>(rx, ry, a.nx, a.ny);
+        const PlaneOffs qring = plane_offs<sizeof(W)>(rx, ry, a.nx, a.ny);
         const uint32_t rxy = reservoir_xy_bits(a, rx, ry);
         // n_s cells of this thread (LDS index, in-plane index); past the list
         // a thread repeats its first cell, the corner (x0 - 1, y0 - 1)
@@ -1471,7 +1496,7 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
                 no[k] = ns_off0;
             }
         }
-        uint32_t er[kQ];
+        W er[kQ];
         float nsv[NSR][CNS];
         auto issue_ring = [&](int p) {
             issue(p, qring, er);
@@ -1527,8 +1552,8 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
     const int x = x0 + min(lx, TXe - 1);
     const int y = y0 + min(ly, TYe - 1);
     const int me = (y - y0 + 1) * LW + (x - x0 + 1);
-    const PlaneOffs qme = plane_offs<4>(x, y, a.nx, a.ny);
-    const uint32_t own = static_cast<uint32_t>(y * a.nx + x) * 4u;
+    const PlaneOffs qme = plane_offs<sizeof(W)>(x, y, a.nx, a.ny);
+    const uint32_t own = static_cast<uint32_t>(y * a.nx + x) * static_cast<uint32_t>(sizeof(W));
     const uint32_t t_key = fmix32(t ^ kGolden);  // stochastic rounding: time part of the counter
     const uint32_t cxy = reservoir_xy_bits(a, x, y);
 
@@ -1600,13 +1625,12 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
             r1 = fmix32(t_key ^ (2u * cell + 1u));
         }
         const uint32_t sr_mask = RND == kRoundEither ? 0u - static_cast<uint32_t>(a.sr != 0) : 0u;
-        auto word = [&](T v0, T v1, uint32_t ra, uint32_t rb) -> uint32_t {
+        auto word = [&](T v0, T v1, uint32_t ra, uint32_t rb) -> W {
             if constexpr (RND == kRoundStochastic) return PC::enc_sr(v0, v1, ra, rb);
             else if constexpr (RND == kRoundNearest) return PC::enc(v0, v1);
             else return (PC::enc_sr(v0, v1, ra, rb) & sr_mask) | (PC::enc(v0, v1) & ~sr_mask);
         };
-        __builtin_amdgcn_raw_buffer_store_b32(word(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), r0, r1), rz, own, 0u,
-                                              kNT);
+        word_store<W>(word(rest(k0, g0, h0(0)), rest(k1, g1, h1(0)), r0, r1), rz, own, 0u);
 #pragma unroll
         for (int i = 1; i <= 9; ++i) {
             T pi0, po0, pi1, po1;
@@ -1619,10 +1643,8 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
                 r0 = lcg24(ri0);
                 r1 = lcg24(ri1);
             }
-            __builtin_amdgcn_raw_buffer_store_b32(word(pi0, pi1, ri0, ri1), rz, own,
-                                                  static_cast<uint32_t>(i) * dir_bytes, kNT);
-            __builtin_amdgcn_raw_buffer_store_b32(word(po0, po1, r0, r1), rz, own,
-                                                  static_cast<uint32_t>(i + 9) * dir_bytes, kNT);
+            word_store<W>(word(pi0, pi1, ri0, ri1), rz, own, static_cast<uint32_t>(i) * dir_bytes);
+            word_store<W>(word(po0, po1, r0, r1), rz, own, static_cast<uint32_t>(i + 9) * dir_bytes);
         }
     };
 
@@ -1630,7 +1652,7 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         // One cell deep: planes z - 1, z and z + 1 are all plane 0, staged
         // once and collided against itself.
         const int slot = rslot(0);
-        uint32_t r1[kQ];
+        W r1[kQ];
         issue(0, qme, r1);
         T d0, d1, jm[6];
         moments(cxy | reservoir_z_bits(a, 0), r1, d0, d1, jm);
@@ -1639,6 +1661,50 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
         __syncthreads();
         collide(0, slot, slot, slot, jm, [&](int i) { return r1[i]; });
         return;
+    } else if constexpr (sizeof(W) == 8) {
+        // FP32 words: LDS holds one plane of them.  Plane z is collided from
+        // registers (hz), plane z+1 waits in LDS (hs), and the loads of plane
+        // z+2 are in flight over the barrier and the collision.  The ring
+        // waves issue the ring loads of a plane at the same stage as these
+        // own loads, while the neighbouring tiles' copies are still in L2.
+        W* hsl = &sh.hs[0][0][0] + tl;
+        W rc[kQ];
+        W hz[kQ];
+        T jA[6], jB[6];
+        // Stage plane p, whose loads are in rc: densities to LDS, first
+        // moments to jm, the words of the plane before from hs to hz and
+        // plane p's into hs; then the loads of plane pn are issued.
+        auto stage_pipe = [&](int p, int pu, int pn, T (&jm)[6]) {
+            T d0, d1;
+            moments(cxy | reservoir_z_bits(a, p), rc, d0, d1, jm);
+            const int slot = rslot(pu);
+            s_rho[slot][0][me] = d0;
+            s_rho[slot][1][me] = d1;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                hz[i] = hsl[i * NT];
+                hsl[i * NT] = rc[i];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            issue(pn, qme, rc);
+        };
+        auto wd = [&](int i) { return hz[i]; };
+        // the plane whose loads a stage of plane p issues: p + 1, or after the
+        // last plane the one just staged again (cache hits)
+        auto next = [&](int p) { return wrapz(p + 1 <= ze ? p + 1 : ze); };
+        issue(wrapz(zs - 1), qme, rc);
+        stage_pipe(wrapz(zs - 1), zs - 1, zs, jB);
+        stage_pipe(zs, zs, next(zs), jA);
+        // unrolled by two so the moment sets keep fixed names
+        for (int z = zs; z < ze; z += 2) {
+            stage_pipe(wrapz(z + 1), z + 1, next(z + 1), jB);
+            __syncthreads();
+            collide(z, rslot(z - 1), rslot(z), rslot(z + 1), jA, wd);
+            if (z + 1 >= ze) break;
+            stage_pipe(wrapz(z + 2), z + 2, next(z + 2), jA);
+            __syncthreads();
+            collide(z + 1, rslot(z), rslot(z + 1), rslot(z + 2), jB, wd);
+        }
     } else {
         // Three planes at a time: the words of planes z and z+1 wait in LDS
         // (hs, double-buffered), plane z is collided, and the loads of plane
@@ -1694,9 +1760,9 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a, const uint3
     }
 }
 
-// Two components in a 16-bit format use the pair layout and kernel.
+// Two components in FP32 or a 16-bit format use the pair layout and kernel.
 template <typename ST, int NC>
-constexpr bool kPair = sizeof(typename ST::E) == 2 && NC == 2;
+constexpr bool kPair = (sizeof(typename ST::E) == 2 || std::is_same_v<ST, F32>) && NC == 2;
 
 template <typename ST, int NC, int TX, int TY>
 constexpr int kThreads = kPair<ST, NC> ? TX * TY + kPairRing : NC * TX * TY;
@@ -1713,9 +1779,10 @@ __global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step(Args<typena
     int L = blockIdx.x;
     if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
     if constexpr (kPair<ST, NC>) {
-        __shared__ PairShared<CNS, TX, TY> sh;
-        step_tile_pair<ST, CNS, TX, TY, FS, ONE, RND>(a, reinterpret_cast<const uint32_t*>(A),
-                                                      reinterpret_cast<uint32_t*>(B), ns, L, a.t, sh);
+        using W = typename PairWordOf<ST>::W;
+        __shared__ PairShared<ST, CNS, TX, TY> sh;
+        step_tile_pair<ST, CNS, TX, TY, FS, ONE, RND>(a, reinterpret_cast<const W*>(A), reinterpret_cast<W*>(B), ns, L,
+                                                      a.t, sh);
     } else {
         __shared__ TileShared<ST, NC, CNS, TX, TY> sh;
         step_tile<ST, NC, CNS, TX, TY, FS, ONE>(a, A, B, ns, L, a.t, sh);
@@ -1762,7 +1829,7 @@ __global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step_batch(const
     // (neighbouring tiles re-read each other's edge cells through its L2)
     const int nb = gridDim.x;
     const int b0 = (nb & 7) == 0 ? (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
-    using Shared = std::conditional_t<kPair<ST, NC>, PairShared<CNS, TX, TY>, TileShared<ST, NC, CNS, TX, TY>>;
+    using Shared = std::conditional_t<kPair<ST, NC>, PairShared<ST, CNS, TX, TY>, TileShared<ST, NC, CNS, TX, TY>>;
     __shared__ Shared sh;
     for (int w = b0; w < total; w += nb) {
         int lo = 0, hi = nd - 1;  // last domain with tile_begin <= w
@@ -1777,12 +1844,15 @@ __global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step_batch(const
         __syncthreads();  // the previous tile's LDS is no longer read
         if constexpr (kPair<ST, NC>) {
             // the rounding of each domain picks a tile sweep compiled for it
-            const uint32_t* src = static_cast<const uint32_t*>(e.buf[cur]);
-            uint32_t* dst = static_cast<uint32_t*>(const_cast<void*>(e.buf[1 - cur]));
+            // (FP32 rounds to nearest only)
+            using W = typename PairWordOf<ST>::W;
+            const W* src = static_cast<const W*>(e.buf[cur]);
+            W* dst = static_cast<W*>(const_cast<void*>(e.buf[1 - cur]));
             const uint32_t tk = e.a.t + static_cast<uint32_t>(k);
+            constexpr int SR = sizeof(E) == 2 ? kRoundStochastic : kRoundNearest;
             if (e.a.sr)
-                step_tile_pair<ST, CNS, TX, TY, kForcingShanChen, false, kRoundStochastic>(e.a, src, dst, e.ns,
-                                                                                         w - e.tile_begin, tk, sh);
+                step_tile_pair<ST, CNS, TX, TY, kForcingShanChen, false, SR>(e.a, src, dst, e.ns, w - e.tile_begin,
+                                                                             tk, sh);
             else
                 step_tile_pair<ST, CNS, TX, TY, kForcingShanChen, false, kRoundNearest>(e.a, src, dst, e.ns,
                                                                                       w - e.tile_begin, tk, sh);
@@ -2238,7 +2308,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
 // ---------------------------------------------------------------------------
 // Launchers.
 
-bool pair_layout(int storage, int ncomp) { return (storage == kF16 || storage == kBF16) && ncomp == 2; }
+bool pair_layout(int storage, int ncomp) { return (storage == kF32 || storage == kF16 || storage == kBF16) && ncomp == 2; }
 
 int pair_tile_y() { return kPairTY; }
 
@@ -2275,8 +2345,9 @@ static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const voi
     // the pair kernel is compiled per rounding mode; the split kernels
     // branch on it (their two store sequences are alike)
     if constexpr (kPair<ST, NC>) {
+        constexpr int SR = sizeof(E) == 2 ? kRoundStochastic : kRoundNearest;  // FP32 rounds to nearest
         if (p.stochastic)
-            hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, kRoundStochastic>), dim3(nblocks),
+            hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, SR>), dim3(nblocks),
                                dim3(kThreads<ST, NC, TX, TY>), 0, st, a, static_cast<const E*>(A), static_cast<E*>(B), ns);
         else
             hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, kRoundNearest>), dim3(nblocks),
