@@ -63,7 +63,11 @@ def _workload_2d(nx, ny, rho, ns, **kw):
                            name="plane", **kw)
 
 
-def test_quasi_2d_gpu_equals_the_d2q9_oracle():
+# FP64 to 1e-10; FP32 and FP16 (the pair kernel's one-plane instance, with
+# stochastic rounding in FP16) to the accuracy of their storage (measured
+# after 60 steps: 1.6e-6 in FP32, 1.5e-3 in FP16, on u; the rest below)
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5), ("f16s", 5e-3)])
+def test_quasi_2d_gpu_equals_the_d2q9_oracle(storage, tol):
     nx, ny, steps = 70, 37, 60
     g = np.random.default_rng(2024)
     ns = g.choice([0.0, 0.05, 0.4, 0.9, 1.0], size=(2, 1, ny, nx))
@@ -76,20 +80,20 @@ def test_quasi_2d_gpu_equals_the_d2q9_oracle():
     o = Oracle(st, w.ns.astype(np.float64))
     fo = o.run(o.init(rho), steps)
     mo = o.moments(fo)
-    sim = lbm.from_workload(w, storage="f64")
+    sim = lbm.from_workload(w, storage=storage)
     sim.step(steps)
     fg, mg = sim.populations(), sim.moments()
     sim.close()
     P = _projection()
     fg9 = np.einsum("ji,sizyx->sjzyx", P, fg)
-    assert rel_max_err(fg9, fo) < 1e-10
-    for s in range(2):
-        assert rel_max_err(mg["rho"][s], mo["rho"][s]) < 1e-10
-    for a in range(2):
-        assert rel_max_err(mg["u"][a], mo["u"][a]) < 1e-10
-    # no flow out of the plane, up to rounding
-    assert np.abs(mg["u"][2]).max() < 1e-12 * np.abs(mg["u"][:2]).max()
-    assert rel_max_err(mg["p"], mo["p"]) < 1e-10
+    errs = [rel_max_err(fg9, fo)] + [rel_max_err(mg["rho"][s], mo["rho"][s]) for s in range(2)] + \
+        [rel_max_err(mg["u"][a], mo["u"][a]) for a in range(2)] + [rel_max_err(mg["p"], mo["p"])]
+    print(storage, ["%.1e" % e for e in errs])
+    assert max(errs) < tol, (storage, errs)
+    # no flow out of the plane, up to rounding (stochastic rounding treats the
+    # mirror images c_z = +1 and -1 of a population with different random bits)
+    uz_tol = tol if storage == "f16s" else 1e-12
+    assert np.abs(mg["u"][2]).max() < uz_tol * np.abs(mg["u"][:2]).max()
 
 
 @pytest.mark.parametrize("row", [1, 2, 3, 4])
