@@ -43,15 +43,17 @@ struct Launch {
 };
 
 // True if two components in this format use the pair layout: both values of
-// one (cell, direction) in one word (FP32 and the 16-bit formats), plane
-// blocks [z][i][y][x][s]; all other runs use the split layout [s][z][i][y][x].
-bool pair_layout(int storage, int ncomp);
+// one (cell, direction) in one word (FP32 and the 16-bit formats; FP32 with
+// the GS-WBS keeps the split layout), plane blocks [z][i][y][x][s]; all other
+// runs use the split layout [s][z][i][y][x].
+bool pair_layout(int storage, int ncomp, int forcing = kForcingShanChen);
 
 // Rows of the default tile of the pair kernel (64 cells wide).
 int pair_tile_y();
 
-// True if the tile shape is compiled in for this format and component count.
-bool tile_supported(int storage, int ncomp, int tile_x, int tile_y);
+// True if the tile shape is compiled in for this format, component count and
+// forcing scheme.
+bool tile_supported(int storage, int ncomp, int tile_x, int tile_y, int forcing = kForcingShanChen);
 
 // Bytes per stored population.
 int storage_bytes(int storage);

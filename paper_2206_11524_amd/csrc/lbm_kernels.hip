@@ -330,7 +330,7 @@ static Args<T> make_args(const Problem& p)
     a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
     a.plane = p.nx * p.ny;
     a.N = p.N;
-    a.pair = pair_layout(p.storage, p.ncomp) ? 1 : 0;
+    a.pair = pair_layout(p.storage, p.ncomp, p.forcing) ? 1 : 0;
     for (int s = 0; s < 2; ++s) {
         a.tau[s] = static_cast<T>(p.tau[s]);
         a.inv_tau[s] = static_cast<T>(1.0 / p.tau[s]);
@@ -1760,15 +1760,19 @@ __device__ __forceinline__ void step_tile_pair(const Args<float>& a,
     }
 }
 
-// Two components in FP32 or a 16-bit format use the pair layout and kernel.
-template <typename ST, int NC>
-constexpr bool kPair = (sizeof(typename ST::E) == 2 || std::is_same_v<ST, F32>) && NC == 2;
+// Two components in FP32 or a 16-bit format use the pair layout and kernel,
+// except FP32 with the GS-WBS: its collision, with both components' Guo
+// terms, needs more registers than the FP32 pair sweep leaves (it spilled and
+// ran 4.6 % slower than in the split layout).
+template <typename ST, int NC, int FS = kForcingShanChen>
+constexpr bool kPair =
+    (sizeof(typename ST::E) == 2 || (std::is_same_v<ST, F32> && FS != kForcingGuo)) && NC == 2;
 
-template <typename ST, int NC, int TX, int TY>
-constexpr int kThreads = kPair<ST, NC> ? TX * TY + kPairRing : NC * TX * TY;
+template <typename ST, int NC, int TX, int TY, int FS = kForcingShanChen>
+constexpr int kThreads = kPair<ST, NC, FS> ? TX * TY + kPairRing : NC * TX * TY;
 
 template <typename ST, int NC, int CNS, int TX, int TY, int FS, bool ONE, int RND>
-__global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step(Args<typename ST::T> a,
+__global__ __launch_bounds__((kThreads<ST, NC, TX, TY, FS>)) void k_step(Args<typename ST::T> a,
                                                                     const typename ST::E* __restrict__ A,
                                                                     typename ST::E* __restrict__ B,
                                                                     const float* __restrict__ ns)
@@ -1778,7 +1782,7 @@ __global__ __launch_bounds__((kThreads<ST, NC, TX, TY>)) void k_step(Args<typena
     const int nb = gridDim.x;
     int L = blockIdx.x;
     if ((nb & 7) == 0) L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    if constexpr (kPair<ST, NC>) {
+    if constexpr (kPair<ST, NC, FS>) {
         using W = typename PairWordOf<ST>::W;
         __shared__ PairShared<ST, CNS, TX, TY> sh;
         step_tile_pair<ST, CNS, TX, TY, FS, ONE, RND>(a, reinterpret_cast<const W*>(A), reinterpret_cast<W*>(B), ns, L,
@@ -2308,13 +2312,16 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
 // ---------------------------------------------------------------------------
 // Launchers.
 
-bool pair_layout(int storage, int ncomp) { return (storage == kF32 || storage == kF16 || storage == kBF16) && ncomp == 2; }
+bool pair_layout(int storage, int ncomp, int forcing)
+{
+    return ((storage == kF32 && forcing != kForcingGuo) || storage == kF16 || storage == kBF16) && ncomp == 2;
+}
 
 int pair_tile_y() { return kPairTY; }
 
-bool tile_supported(int storage, int ncomp, int tx, int ty)
+bool tile_supported(int storage, int ncomp, int tx, int ty, int forcing)
 {
-    if (pair_layout(storage, ncomp)) return tx == 64 && (ty == kPairTY || ty == 4);
+    if (pair_layout(storage, ncomp, forcing)) return tx == 64 && (ty == kPairTY || ty == 4);
     return (tx == 128 && ty == 4) || (tx == 64 && (ty == 4 || ty == 8)) || (tx == 32 && (ty == 4 || ty == 8 || ty == 16));
 }
 
@@ -2344,17 +2351,20 @@ static hipError_t step_t(const Problem& p, const Launch& l, int64_t t, const voi
     const int nblocks = a.ntx * a.nty * a.nzc;
     // the pair kernel is compiled per rounding mode; the split kernels
     // branch on it (their two store sequences are alike)
-    if constexpr (kPair<ST, NC>) {
+    if constexpr (kPair<ST, NC, FS>) {
         constexpr int SR = sizeof(E) == 2 ? kRoundStochastic : kRoundNearest;  // FP32 rounds to nearest
         if (p.stochastic)
             hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, SR>), dim3(nblocks),
-                               dim3(kThreads<ST, NC, TX, TY>), 0, st, a, static_cast<const E*>(A), static_cast<E*>(B), ns);
+                               dim3(kThreads<ST, NC, TX, TY, FS>), 0, st, a, static_cast<const E*>(A),
+                               static_cast<E*>(B), ns);
         else
             hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, kRoundNearest>), dim3(nblocks),
-                               dim3(kThreads<ST, NC, TX, TY>), 0, st, a, static_cast<const E*>(A), static_cast<E*>(B), ns);
+                               dim3(kThreads<ST, NC, TX, TY, FS>), 0, st, a, static_cast<const E*>(A),
+                               static_cast<E*>(B), ns);
     } else {
         hipLaunchKernelGGL((k_step<ST, NC, CNS, TX, TY, FS, ONE, kRoundEither>), dim3(nblocks),
-                           dim3(kThreads<ST, NC, TX, TY>), 0, st, a, static_cast<const E*>(A), static_cast<E*>(B), ns);
+                           dim3(kThreads<ST, NC, TX, TY, FS>), 0, st, a, static_cast<const E*>(A), static_cast<E*>(B),
+                           ns);
     }
     return hipGetLastError();
 }

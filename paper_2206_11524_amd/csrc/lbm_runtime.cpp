@@ -98,13 +98,13 @@ hm::Launch choose_launch(const hm::Problem& p, int cus)
     // register file (no spills); the pair kernel runs one thread per cell
     // plus three ring waves on 64-wide tiles of pair_tile_y() rows
     const bool wide = p.storage == hm::kF64 && p.ncomp == 2;
-    const bool pair = hm::pair_layout(p.storage, p.ncomp);
+    const bool pair = hm::pair_layout(p.storage, p.ncomp, p.forcing);
     const int pty = hm::pair_tile_y();
     const int dflt_y = pair ? (p.ny >= pty ? pty : 4) : ((p.ny >= 8 && !wide) ? 8 : 4);
     l.tile_x = env_int("LBM_TILE_X", 64);
     l.tile_y = env_int("LBM_TILE_Y", dflt_y);
     // the GS-WBS and one-plane domains use the default tile widths only
-    if (!hm::tile_supported(p.storage, p.ncomp, l.tile_x, l.tile_y) ||
+    if (!hm::tile_supported(p.storage, p.ncomp, l.tile_x, l.tile_y, p.forcing) ||
         ((p.forcing == hm::kForcingGuo || p.nz == 1) &&
          !(l.tile_x == 64 && (pair ? (l.tile_y == pty || l.tile_y == 4) : (l.tile_y == 8 || l.tile_y == 4))))) {
         l.tile_x = 64;
