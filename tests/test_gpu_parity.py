@@ -161,17 +161,30 @@ def test_droplet_fp32_fields():
 _U = {"f32": 2.0 ** -24, "f16s": 2.0 ** -11, "bf16s": 2.0 ** -8}
 
 
+def _ragged_all_features():
+    """A ragged domain (70 x 13 x 11: partial tiles in x and y) with one n_s
+    field per component, density reservoirs on z and every force term."""
+    w = inputs.random_state((70, 13, 11), 41, c_ns=2, ns_choices=[0.0, 0.2, 0.7, 1.0], rho_range=(0.3, 0.7))
+    w.G, w.G_ads, w.F_ext = 0.8, (0.15, -0.2), (2e-4, -1e-4, 3e-4)
+    w.reservoirs = [(2, 0, 2, (0.65, 0.3)), (2, 9, 11, (0.3, 0.65))]
+    return w
+
+
+@pytest.mark.parametrize("case", ["droplet", "ragged"])
 @pytest.mark.parametrize("storage,rounding", [("f32", "nearest"), ("f16s", "nearest"), ("bf16s", "nearest"),
                                               ("f16s", "stochastic"), ("bf16s", "stochastic")])
-def test_one_step_error_is_the_storage_rounding(storage, rounding):
+def test_one_step_error_is_the_storage_rounding(storage, rounding, case):
     """From a state held exactly in the storage format, one GPU step differs
     from the FP64 oracle's step of the same state by the rounding of the stored
     result plus FP32 arithmetic: |f_gpu - f_ref| <= k u |h_ref| + 2e-6 max|f|
     with u the unit roundoff, k = 1 for rounding to nearest (half a unit in the
-    last place) and k = 2 for stochastic rounding (less than one unit)."""
+    last place) and k = 2 for stochastic rounding (less than one unit).  On the
+    24^3 droplet and on a ragged domain with two n_s fields, reservoirs and
+    every force term (the pair kernel's partial tiles, membranes and
+    reservoir override in FP32 and 16-bit)."""
     import oracle
     _, w19, _ = oracle.lattice(19)
-    w = inputs.droplet(n=24, radius=6)
+    w = inputs.droplet(n=24, radius=6) if case == "droplet" else _ragged_all_features()
     o = oracle_for(w)
     f0 = o.run(o.init(w.rho), 30)
     sim = lbm.from_workload(w, storage=storage, rounding=rounding)
